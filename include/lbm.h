@@ -1,0 +1,197 @@
+/*
+ * lbm.h -- C-ABI of the MI355X (gfx950) axisymmetric thermal lattice
+ * Boltzmann LES solver: D2Q9 flow populations, D2Q4 temperature populations,
+ * local Smagorinsky relaxation time, temperature-dependent properties and the
+ * axisymmetric source terms, one fused collide-and-stream update per step.
+ *
+ * Method (Djebali, Calve, Pateyron, El Ganaoui, Sammouda):
+ *   section 2.1, eq. (1)   two LBGK updates with sources F1, F2, S;
+ *   section 2.1, eq. (2)   moments rho, u, T;
+ *   text after eq. (1)     nu = (tau_nu - 1/2)/3, alpha = (tau_alpha - 1/2)/2;
+ *   section 2.2, eqs. 3-5  Smagorinsky closure, closed-form tau_tot,
+ *                          alpha_tot = alpha + nu_t / Pr_t;
+ *   section 2.3, eq. (6)   nu(T), alpha(T) from multiplier tables;
+ *   section 2.4, eq. (7)   inlet profiles, given here as inlet rows.
+ * The source terms are not printed in the paper; the library uses the forms
+ * derived from the axisymmetric Navier-Stokes and energy equations:
+ *   F1 -> w_k theta, theta = -rho u_r / r;
+ *   F2 -> F_x = -rho u_x u_r / r - (1 - 1/(2 tau)) Q_xr / r + rho G,
+ *         F_r = -rho u_r^2 / r - (1 - 1/(2 tau)) Q_rr / r - 2 rho nu_tot u_r / D,
+ *         D = r^2 (hoop = 0) or r^2 + 2 nu_tot (hoop = 1), weight e_k . F / 6;
+ *   S  -> S/4 per link, S = -T u_r / r - (1 - 1/(2 tau_a)) sum_k e_kr g_k^neq / r.
+ *
+ * Lattice units (dx = dt = 1).  Node (i, j) sits at x = i, r = r0 + j + 1/2;
+ * i = 0..nx-1 is axial (fastest in every array), j = 0..nr-1 radial.
+ *
+ * Conventions shared by all calls:
+ *   - Return 0 (LBM_OK) or a negative LBM_E* code; nothing prints or aborts.
+ *   - Input pointers are borrowed for the duration of the call (copied).
+ *   - Host arrays are caller-allocated; device memory handed in through
+ *     lbm_create_in must outlive the handle and is never freed by the library.
+ *   - Work is enqueued on the handle's HIP stream; lbm_step may return before
+ *     the work completes.  Asynchronous failures (device errors, a non-finite
+ *     or non-positive density seen by the step) are reported by the next
+ *     synchronising call (lbm_moments, lbm_profiles, lbm_conservation,
+ *     lbm_get_populations, lbm_sync) and by every later lbm_step.
+ *   - LBM_EUNSTABLE is sticky until lbm_set_state or lbm_set_populations.
+ *   - A handle is used by one host thread at a time; handles are independent.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_ABI_VERSION 1u
+
+enum lbm_status {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,     /* invalid argument or configuration               */
+  LBM_ENOMEM = -2,     /* device or host allocation failed, budget full    */
+  LBM_EUNSTABLE = -3,  /* non-finite value or rho <= 0 seen                */
+  LBM_EDEVICE = -4,    /* HIP runtime error                                */
+  LBM_ESTATE = -5      /* call not valid in the handle's current state     */
+};
+
+/* Population storage.  Arithmetic is FP32 in every case. */
+enum lbm_precision {
+  LBM_PREC_FP32 = 1,     /* 13 x 4 B per node                                */
+  LBM_PREC_FP16DEV = 2,  /* binary16 of f_k - w_k rho_ref, g_k - g_ref/4     */
+  LBM_PREC_BF16DEV = 3   /* bfloat16 of the same deviations                  */
+};
+
+/* Edge rules, per side: 0 = x0 (i = -1), 1 = x1 (i = nx), 2 = r0 (j = -1),
+ * 3 = r1 (j = nr).  Rules on the r sides are applied first; a mirrored pull
+ * then goes through the x-side rule at the edge row. */
+enum lbm_bc {
+  LBM_BC_INLET = 0,    /* x0: equilibrium at rho = 1 and the inlet row      */
+  LBM_BC_OUTFLOW = 1,  /* x1: zero-gradient copy of column nx-1             */
+  LBM_BC_PERIODIC = 2, /* x0 and x1 together                                */
+  LBM_BC_AXIS = 3,     /* r0 with r0 == 0: half-way specular symmetry axis  */
+  LBM_BC_FREESLIP = 4, /* r sides: half-way specular mirror                 */
+  LBM_BC_WALL = 5,     /* any side: half-way bounce-back; anti-bounce-back
+                          for g at the Dirichlet temperature wall_T[side],
+                          plain bounce-back (adiabatic) if wall_T is NaN    */
+  LBM_BC_EQ = 6        /* any side: equilibrium of eq_state[side]           */
+};
+
+typedef struct lbm_handle lbm_handle;
+
+typedef struct {
+  uint32_t abi_version;       /* must be LBM_ABI_VERSION                      */
+  int32_t nx, nr;             /* fluid nodes; >= 2 each                       */
+  double r0;                  /* radius offset; 0 when bc[2] is AXIS          */
+  double tau_nu, tau_alpha;   /* base relaxation times; > 1/2                 */
+  double cs, delta, pr_t;     /* C_s >= 0, filter width > 0, Pr_t > 0         */
+  int32_t table_n;            /* 0: constant properties; else >= 2 entries    */
+  const double *nu_mult;      /* table_n multipliers of nu over [t_lo, t_hi]  */
+  const double *alpha_mult;   /* table_n multipliers of alpha                 */
+  double t_lo, t_hi;          /* uniform table grid; linear, clamped          */
+  int32_t bc[4];              /* LBM_BC_* of x0, x1, r0, r1                   */
+  double wall_T[4];           /* WALL temperature per side; NaN = adiabatic   */
+  double eq_state[4][4];      /* EQ side state rho, ux, ur, T                 */
+  double body_force_x;        /* G; rho G is added to F_x                     */
+  double rho0, ux0, ur0, T0;  /* uniform initial state (equilibrium)          */
+  int32_t hoop;               /* 0: explicit hoop term, 1: stabilised         */
+  int32_t precision;          /* LBM_PREC_*                                   */
+  double rho_ref, g_ref;      /* 16-bit storage offsets (ignored for FP32)    */
+} lbm_config;
+
+/* Device bytes lbm_create_in needs for the two population buffers. */
+int lbm_bytes_required(const lbm_config *cfg, size_t *bytes);
+
+/* Create a solver on the current HIP device, populations at the
+ * equilibrium of (rho0, ux0, ur0, T0), step 0, inlet rows at the ambient
+ * state (u = 0, T = T0).  lbm_create allocates the population buffers and a
+ * stream itself; lbm_create_in uses dev_buf (>= lbm_bytes_required bytes,
+ * 256-byte aligned) and hip_stream (a hipStream_t; NULL = default stream),
+ * both owned by the caller.  *out is NULL on failure. */
+int lbm_create(const lbm_config *cfg, lbm_handle **out);
+int lbm_create_in(const lbm_config *cfg, void *dev_buf, size_t bytes,
+                  void *hip_stream, lbm_handle **out);
+
+/* Inlet rows for the x0 INLET edge (eq. 7 profiles, or any other):
+ * n_t rows of nr values each, row-major; step s uses row s mod n_t. */
+int lbm_set_inlet(lbm_handle *h, int32_t n_t, const double *ux, const double *ur,
+                  const double *T);
+
+/* Advance n_steps >= 0 steps (eq. 1 on every node).  Enqueues only. */
+int lbm_step(lbm_handle *h, int64_t n_steps);
+
+/* Pre-collision moments (eq. 2) at the current step, each nr*nx doubles;
+ * NULL pointers are skipped.  Synchronises. */
+int lbm_moments(lbm_handle *h, double *rho, double *ux, double *ur, double *T);
+
+void lbm_destroy(lbm_handle *h); /* NULL-safe; waits for queued work */
+
+/* ---- extras ------------------------------------------------------------- */
+int64_t lbm_step_count(const lbm_handle *h); /* -1 for NULL */
+void *lbm_stream(const lbm_handle *h);       /* the handle's hipStream_t    */
+int lbm_sync(lbm_handle *h);                 /* wait; report async errors   */
+/* Group k steps into one HIP graph launch (0 disables graphs). */
+int lbm_set_graph_steps(lbm_handle *h, int32_t k);
+/* Equilibrium fill from fields (each nr*nx); clears LBM_EUNSTABLE. */
+int lbm_set_state(lbm_handle *h, const double *rho, const double *ux,
+                  const double *ur, const double *T);
+/* Stored post-collision populations, decoded to double: f 9*nr*nx, g 4*nr*nx
+ * (population index slowest). */
+int lbm_get_populations(lbm_handle *h, double *f, double *g);
+int lbm_set_populations(lbm_handle *h, const double *f, const double *g,
+                        int64_t step);
+/* FP64 reductions of the step's pre-collision moments:
+ * mass3d = sum_ij r_j rho_ij, energy3d = sum_ij r_j T_ij. */
+int lbm_conservation(lbm_handle *h, double *mass3d, double *energy3d);
+/* Centreline (j = 0) u_x and T, nx each; exit column (i = nx-1), nr each. */
+int lbm_profiles(lbm_handle *h, double *ux_axis, double *T_axis,
+                 double *ux_exit, double *T_exit);
+const char *lbm_strerror(int code);
+
+/* Measurement helper: copy `bytes` (multiple of 16) from src to dst on the
+ * device with a plain streaming kernel, on hip_stream.  Used to calibrate
+ * the HBM traffic counters against a transfer of known size. */
+int lbm_probe_copy(void *dst, const void *src, size_t bytes, void *hip_stream);
+
+/* ---- many jets in one persistent launch ----------------------------------
+ * A batch owns up to max_slots resident jets whose population buffers are
+ * carved out of budget_bytes of device memory.  lbm_batch_run advances every
+ * active jet by up to k steps with one launch per step (grouped into HIP
+ * graphs); a jet stops at its own target step count.  Each jet's result is
+ * bitwise the same as that of the same jet run alone through the batch.
+ * Precision is common to the batch. */
+typedef struct lbm_batch lbm_batch;
+int lbm_batch_create(size_t budget_bytes, int32_t max_slots, int32_t precision,
+                     void *hip_stream, lbm_batch **out);
+/* Admit a jet (cfg->precision is ignored).  LBM_ENOMEM when the budget or the
+ * slot table is full.  n_t/ux/ur/T as lbm_set_inlet (n_t = 0: ambient). */
+int lbm_batch_admit(lbm_batch *b, const lbm_config *cfg, int32_t n_t,
+                    const double *ux, const double *ur, const double *T,
+                    int64_t target_steps, int32_t *slot);
+int lbm_batch_run(lbm_batch *b, int32_t k_steps);
+/* Steps done by a slot's jet (host-side count; exact after lbm_batch_run). */
+int lbm_batch_poll(lbm_batch *b, int32_t slot, int64_t *steps_done);
+int lbm_batch_profiles(lbm_batch *b, int32_t slot, double *ux_axis, double *T_axis,
+                       double *ux_exit, double *T_exit);
+int lbm_batch_moments(lbm_batch *b, int32_t slot, double *rho, double *ux,
+                      double *ur, double *T);
+int lbm_batch_retire(lbm_batch *b, int32_t slot);
+/* Bytes a jet of this configuration takes from the budget. */
+int lbm_batch_jet_bytes(const lbm_batch *b, const lbm_config *cfg, size_t *bytes);
+int lbm_batch_active(const lbm_batch *b, int32_t *n_active, size_t *bytes_used);
+/* Tile shape of the step kernel (index into the compiled shapes; -1 = auto)
+ * and the number of persistent workgroups (0 = auto). */
+int lbm_batch_set_launch(lbm_batch *b, int32_t tile_shape, int32_t workgroups);
+void lbm_batch_destroy(lbm_batch *b);
+
+/* Compiled tile shapes of the step kernel: count, and (bx, by, ny) of one. */
+int lbm_tile_shape_count(void);
+int lbm_tile_shape(int32_t index, int32_t *bx, int32_t *by, int32_t *ny);
+int lbm_set_tile_shape(lbm_handle *h, int32_t index);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

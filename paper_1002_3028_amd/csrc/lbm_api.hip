@@ -1,0 +1,468 @@
+// lbm_api.hip -- single-jet C-ABI (include/lbm.h) on one HIP device.
+//
+// A handle owns (or borrows) two population buffers and a stream, plus a few
+// small device arrays: the descriptor, a one-entry tile list, the property
+// table, the inlet rows and an instability flag.  Steps are enqueued as one
+// launch of the step kernel each, or as HIP graphs of k launches followed
+// by the descriptor advance.
+#include "lbm_runtime.hpp"
+
+using namespace lbmx;
+
+struct lbm_handle {
+  int device = 0;
+  lbm_config cfg{};
+  std::vector<double> nu_tab, al_tab;
+  int prec = LBM_PREC_FP32;
+  void *buf = nullptr;
+  bool own_buf = false;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  // device arrays
+  JetDesc *d_desc = nullptr;
+  int32_t *d_tiles = nullptr;
+  BatchHdr *d_hdr = nullptr;
+  int32_t *d_flag = nullptr;
+  float4 *d_table = nullptr;
+  float4 *d_inlet = nullptr;
+  Scratch scratch;
+  JetDesc desc{};
+  int64_t step = 0;  // steps done
+  int64_t base = 0;  // step0 held by the device descriptor
+  int shape = 0;
+  int32_t ntiles = 0, grid = 0;
+  bool unstable = false;
+  int32_t graph_k = 0;
+  hipGraphExec_t gexec = nullptr;
+  int32_t gexec_k = 0, gexec_shape = -1;
+};
+
+namespace {
+
+int upload_desc(lbm_handle *h) {
+  h->desc.step0 = h->base;
+  LBM_HIP(hipMemcpyAsync(h->d_desc, &h->desc, sizeof(JetDesc), hipMemcpyHostToDevice, h->stream));
+  LBM_HIP(hipStreamSynchronize(h->stream));
+  return LBM_OK;
+}
+
+int set_shape(lbm_handle *h, int shape) {
+  int n;
+  tile_shapes(&n);
+  if (shape < 0 || shape >= n) return LBM_EINVAL;
+  int32_t tx;
+  h->ntiles = tiles_of(&h->cfg, shape, &tx);
+  h->grid = (h->ntiles + 7) / 8 * 8;
+  h->shape = shape;
+  h->desc.tiles_x = tx;
+  int32_t tl[2] = {0, h->ntiles};
+  LBM_HIP(hipMemcpyAsync(h->d_tiles, tl, sizeof tl, hipMemcpyHostToDevice, h->stream));
+  return upload_desc(h);
+}
+
+void drop_graph(lbm_handle *h) {
+  if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+  h->gexec = nullptr;
+  h->gexec_k = 0;
+  h->gexec_shape = -1;
+}
+
+// Sync, then fold the device instability flag into the sticky state.
+int sync_and_check(lbm_handle *h) {
+  LBM_HIP(hipStreamSynchronize(h->stream));
+  LBM_HIP(hipGetLastError());
+  int32_t flag = 0;
+  LBM_HIP(hipMemcpy(&flag, h->d_flag, sizeof flag, hipMemcpyDeviceToHost));
+  if (flag) h->unstable = true;
+  return h->unstable ? LBM_EUNSTABLE : LBM_OK;
+}
+
+int clear_flag(lbm_handle *h) {
+  const int32_t zero = 0;
+  LBM_HIP(hipMemcpy(h->d_flag, &zero, sizeof zero, hipMemcpyHostToDevice));
+  h->unstable = false;
+  return LBM_OK;
+}
+
+void release(lbm_handle *h) {
+  if (!h) return;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  drop_graph(h);
+  h->scratch.release();
+  if (h->d_desc) (void)hipFree(h->d_desc);
+  if (h->d_tiles) (void)hipFree(h->d_tiles);
+  if (h->d_hdr) (void)hipFree(h->d_hdr);
+  if (h->d_flag) (void)hipFree(h->d_flag);
+  if (h->d_table) (void)hipFree(h->d_table);
+  if (h->d_inlet) (void)hipFree(h->d_inlet);
+  if (h->own_buf && h->buf) (void)hipFree(h->buf);
+  if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+  delete h;
+}
+
+int upload_inlet(lbm_handle *h, const std::vector<float4> &rows, int32_t n_t) {
+  float4 *p = nullptr;
+  LBM_HIP(hipStreamSynchronize(h->stream));
+  if (hipMalloc(&p, rows.size() * sizeof(float4)) != hipSuccess) return LBM_ENOMEM;
+  if (hipMemcpy(p, rows.data(), rows.size() * sizeof(float4), hipMemcpyHostToDevice) !=
+      hipSuccess) {
+    (void)hipFree(p);
+    return LBM_EDEVICE;
+  }
+  if (h->d_inlet) (void)hipFree(h->d_inlet);
+  h->d_inlet = p;
+  h->desc.inlet = p;
+  h->desc.n_t = n_t;
+  return upload_desc(h);
+}
+
+int create_common(const lbm_config *cfg, void *dev_buf, size_t bytes, void *stream,
+                  lbm_handle **out) {
+  if (!out) return LBM_EINVAL;
+  *out = nullptr;
+  int rc = validate_config(cfg, true);
+  if (rc) return rc;
+  lbm_handle *h = new (std::nothrow) lbm_handle();
+  if (!h) return LBM_ENOMEM;
+  h->cfg = *cfg;
+  if (cfg->table_n > 0) {
+    h->nu_tab.assign(cfg->nu_mult, cfg->nu_mult + cfg->table_n);
+    h->al_tab.assign(cfg->alpha_mult, cfg->alpha_mult + cfg->table_n);
+    h->cfg.nu_mult = h->nu_tab.data();
+    h->cfg.alpha_mult = h->al_tab.data();
+  }
+  h->prec = cfg->precision;
+  if (hipGetDevice(&h->device) != hipSuccess) {
+    release(h);
+    return LBM_EDEVICE;
+  }
+  const size_t one = buffer_bytes(cfg, h->prec);
+  if (dev_buf) {
+    if (bytes < 2 * one || ((uintptr_t)dev_buf & 255)) {
+      release(h);
+      return LBM_EINVAL;
+    }
+    h->buf = dev_buf;
+    h->stream = (hipStream_t)stream;
+  } else {
+    if (hipMalloc(&h->buf, 2 * one) != hipSuccess) {
+      release(h);
+      return LBM_ENOMEM;
+    }
+    h->own_buf = true;
+    if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) {
+      release(h);
+      return LBM_EDEVICE;
+    }
+    h->own_stream = true;
+  }
+  std::vector<float4> table = make_table(&h->cfg);
+  bool ok = hipMalloc(&h->d_desc, sizeof(JetDesc)) == hipSuccess &&
+            hipMalloc(&h->d_tiles, 2 * sizeof(int32_t)) == hipSuccess &&
+            hipMalloc(&h->d_hdr, sizeof(BatchHdr)) == hipSuccess &&
+            hipMalloc(&h->d_flag, sizeof(int32_t)) == hipSuccess &&
+            hipMalloc(&h->d_table, table.size() * sizeof(float4)) == hipSuccess;
+  if (!ok) {
+    release(h);
+    return LBM_ENOMEM;
+  }
+  BatchHdr hdr{1, {0, 0, 0}};
+  const int32_t zero = 0;
+  ok = hipMemcpy(h->d_table, table.data(), table.size() * sizeof(float4),
+                 hipMemcpyHostToDevice) == hipSuccess &&
+       hipMemcpy(h->d_hdr, &hdr, sizeof hdr, hipMemcpyHostToDevice) == hipSuccess &&
+       hipMemcpy(h->d_flag, &zero, sizeof zero, hipMemcpyHostToDevice) == hipSuccess;
+  if (!ok) {
+    release(h);
+    return LBM_EDEVICE;
+  }
+  JetDesc &d = h->desc;
+  fill_desc(d, &h->cfg);
+  d.buf[0] = h->buf;
+  d.buf[1] = (char *)h->buf + one;
+  d.table = h->d_table;
+  d.target = NO_TARGET;
+  d.slot = 0;
+  std::vector<float4> rows;
+  make_inlet(&h->cfg, 0, nullptr, nullptr, nullptr, rows);
+  if ((rc = upload_inlet(h, rows, 1)) || (rc = set_shape(h, default_tile_shape()))) {
+    release(h);
+    return rc;
+  }
+  rc = launch_init(h->prec, h->stream, h->d_desc, &h->cfg, 0, nullptr,
+                   make_float4((float)cfg->rho0, (float)cfg->ux0, (float)cfg->ur0, (float)cfg->T0));
+  if (rc || hipStreamSynchronize(h->stream) != hipSuccess) {
+    release(h);
+    return rc ? rc : LBM_EDEVICE;
+  }
+  *out = h;
+  return LBM_OK;
+}
+
+int launch_steps(lbm_handle *h, int64_t n) {
+  int rc;
+  while (n > 0) {
+    if (h->graph_k > 0 && n >= h->graph_k) {
+      if (h->base != h->step) {  // bring the device step0 to the host count
+        rc = launch_advance(h->stream, h->d_desc, h->d_hdr, 1, (int32_t)(h->step - h->base));
+        if (rc) return rc;
+        h->base = h->step;
+      }
+      if (!h->gexec || h->gexec_k != h->graph_k || h->gexec_shape != h->shape) {
+        drop_graph(h);
+        hipGraph_t g;
+        LBM_HIP(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+        int crc = LBM_OK;
+        for (int32_t k = 0; k < h->graph_k && !crc; ++k)
+          crc = launch_step(h->shape, h->prec, h->grid, h->stream, h->d_desc, h->d_tiles,
+                            h->d_hdr, k, h->d_flag);
+        if (!crc) crc = launch_advance(h->stream, h->d_desc, h->d_hdr, 1, h->graph_k);
+        const hipError_t e = hipStreamEndCapture(h->stream, &g);
+        if (crc || e != hipSuccess) return crc ? crc : LBM_EDEVICE;
+        const hipError_t ei = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) {
+          h->gexec = nullptr;
+          return LBM_EDEVICE;
+        }
+        h->gexec_k = h->graph_k;
+        h->gexec_shape = h->shape;
+      }
+      LBM_HIP(hipGraphLaunch(h->gexec, h->stream));
+      h->step += h->graph_k;
+      h->base += h->graph_k;
+      n -= h->graph_k;
+    } else {
+      int64_t koff = h->step - h->base;
+      if (koff > (1 << 30)) {
+        rc = launch_advance(h->stream, h->d_desc, h->d_hdr, 1, (int32_t)koff);
+        if (rc) return rc;
+        h->base = h->step;
+        koff = 0;
+      }
+      rc = launch_step(h->shape, h->prec, h->grid, h->stream, h->d_desc, h->d_tiles, h->d_hdr,
+                       (int32_t)koff, h->d_flag);
+      if (rc) return rc;
+      h->step += 1;
+      n -= 1;
+    }
+  }
+  return LBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_bytes_required(const lbm_config *cfg, size_t *bytes) {
+  if (!bytes) return LBM_EINVAL;
+  const int rc = validate_config(cfg, true);
+  if (rc) return rc;
+  *bytes = 2 * buffer_bytes(cfg, cfg->precision);
+  return LBM_OK;
+}
+
+int lbm_create(const lbm_config *cfg, lbm_handle **out) {
+  return create_common(cfg, nullptr, 0, nullptr, out);
+}
+
+int lbm_create_in(const lbm_config *cfg, void *dev_buf, size_t bytes, void *hip_stream,
+                  lbm_handle **out) {
+  if (!dev_buf) return out ? (*out = nullptr, LBM_EINVAL) : LBM_EINVAL;
+  return create_common(cfg, dev_buf, bytes, hip_stream, out);
+}
+
+void lbm_destroy(lbm_handle *h) { release(h); }
+
+int lbm_set_inlet(lbm_handle *h, int32_t n_t, const double *ux, const double *ur,
+                  const double *T) {
+  if (!h || n_t < 1) return LBM_EINVAL;
+  std::vector<float4> rows;
+  const int rc = make_inlet(&h->cfg, n_t, ux, ur, T, rows);
+  if (rc) return rc;
+  return upload_inlet(h, rows, n_t);
+}
+
+int lbm_step(lbm_handle *h, int64_t n_steps) {
+  if (!h || n_steps < 0) return LBM_EINVAL;
+  if (h->unstable) return LBM_EUNSTABLE;
+  return launch_steps(h, n_steps);
+}
+
+int64_t lbm_step_count(const lbm_handle *h) { return h ? h->step : -1; }
+
+void *lbm_stream(const lbm_handle *h) { return h ? (void *)h->stream : nullptr; }
+
+int lbm_sync(lbm_handle *h) {
+  if (!h) return LBM_EINVAL;
+  return sync_and_check(h);
+}
+
+int lbm_set_graph_steps(lbm_handle *h, int32_t k) {
+  if (!h || k < 0) return LBM_EINVAL;
+  LBM_HIP(hipStreamSynchronize(h->stream));
+  h->graph_k = k;
+  if (k == 0) drop_graph(h);
+  return LBM_OK;
+}
+
+int lbm_set_tile_shape(lbm_handle *h, int32_t index) {
+  if (!h) return LBM_EINVAL;
+  LBM_HIP(hipStreamSynchronize(h->stream));
+  // bring the descriptor's step0 up to date before re-uploading it
+  h->base = h->step;
+  const int rc = set_shape(h, index);
+  drop_graph(h);
+  return rc;
+}
+
+int lbm_moments(lbm_handle *h, double *rho, double *ux, double *ur, double *T) {
+  if (!h) return LBM_EINVAL;
+  const int64_t nodes = (int64_t)h->cfg.nx * h->cfg.nr;
+  void *p;
+  int rc = h->scratch.get(nodes * sizeof(float4), &p);
+  if (rc) return rc;
+  if ((rc = launch_moments(h->prec, h->stream, h->d_desc, &h->cfg, h->step, (float4 *)p)))
+    return rc;
+  const int st = sync_and_check(h);
+  if (st == LBM_EDEVICE) return st;
+  std::vector<float4> m((size_t)nodes);
+  LBM_HIP(hipMemcpy(m.data(), p, nodes * sizeof(float4), hipMemcpyDeviceToHost));
+  bool finite = true;
+  for (int64_t n = 0; n < nodes; ++n) {
+    if (rho) rho[n] = m[n].x;
+    if (ux) ux[n] = m[n].y;
+    if (ur) ur[n] = m[n].z;
+    if (T) T[n] = m[n].w;
+    finite = finite && std::isfinite(m[n].x) && std::isfinite(m[n].w) && m[n].x > 0.f;
+  }
+  if (!finite) h->unstable = true;
+  return h->unstable ? LBM_EUNSTABLE : LBM_OK;
+}
+
+int lbm_profiles(lbm_handle *h, double *ux_axis, double *T_axis, double *ux_exit,
+                 double *T_exit) {
+  if (!h) return LBM_EINVAL;
+  const int n = h->cfg.nx + h->cfg.nr;
+  void *p;
+  int rc = h->scratch.get(n * sizeof(float2), &p);
+  if (rc) return rc;
+  if ((rc = launch_profiles(h->prec, h->stream, h->d_desc, &h->cfg, h->step, (float2 *)p)))
+    return rc;
+  const int st = sync_and_check(h);
+  if (st == LBM_EDEVICE) return st;
+  std::vector<float2> v(n);
+  LBM_HIP(hipMemcpy(v.data(), p, n * sizeof(float2), hipMemcpyDeviceToHost));
+  for (int i = 0; i < h->cfg.nx; ++i) {
+    if (ux_axis) ux_axis[i] = v[i].x;
+    if (T_axis) T_axis[i] = v[i].y;
+  }
+  for (int j = 0; j < h->cfg.nr; ++j) {
+    if (ux_exit) ux_exit[j] = v[h->cfg.nx + j].x;
+    if (T_exit) T_exit[j] = v[h->cfg.nx + j].y;
+  }
+  return st;
+}
+
+int lbm_conservation(lbm_handle *h, double *mass3d, double *energy3d) {
+  if (!h || !mass3d || !energy3d) return LBM_EINVAL;
+  const int64_t nodes = (int64_t)h->cfg.nx * h->cfg.nr;
+  const int nblocks = (int)std::min<int64_t>(1024, (nodes + RED_THREADS - 1) / RED_THREADS);
+  void *p;
+  int rc = h->scratch.get((nblocks + 1) * sizeof(RedPartial), &p);
+  if (rc) return rc;
+  RedPartial *part = (RedPartial *)p;
+  if ((rc = launch_conservation(h->prec, h->stream, h->d_desc, nodes, h->step, part, nblocks,
+                                part + nblocks)))
+    return rc;
+  const int st = sync_and_check(h);
+  if (st == LBM_EDEVICE) return st;
+  RedPartial r;
+  LBM_HIP(hipMemcpy(&r, part + nblocks, sizeof r, hipMemcpyDeviceToHost));
+  *mass3d = r.mass;
+  *energy3d = r.energy;
+  if (r.bad != 0.0) h->unstable = true;
+  return h->unstable ? LBM_EUNSTABLE : LBM_OK;
+}
+
+int lbm_set_state(lbm_handle *h, const double *rho, const double *ux, const double *ur,
+                  const double *T) {
+  if (!h || !rho || !ux || !ur || !T) return LBM_EINVAL;
+  const int64_t nodes = (int64_t)h->cfg.nx * h->cfg.nr;
+  std::vector<float4> s((size_t)nodes);
+  for (int64_t n = 0; n < nodes; ++n) {
+    if (!(rho[n] > 0.0) || !std::isfinite(rho[n]) || !std::isfinite(ux[n]) ||
+        !std::isfinite(ur[n]) || !std::isfinite(T[n]))
+      return LBM_EINVAL;
+    s[n] = make_float4((float)rho[n], (float)ux[n], (float)ur[n], (float)T[n]);
+  }
+  void *p;
+  int rc = h->scratch.get(nodes * sizeof(float4), &p);
+  if (rc) return rc;
+  LBM_HIP(hipStreamSynchronize(h->stream));
+  LBM_HIP(hipMemcpy(p, s.data(), nodes * sizeof(float4), hipMemcpyHostToDevice));
+  if ((rc = launch_init(h->prec, h->stream, h->d_desc, &h->cfg, h->step, (const float4 *)p,
+                        make_float4(0, 0, 0, 0))))
+    return rc;
+  LBM_HIP(hipStreamSynchronize(h->stream));
+  return clear_flag(h);
+}
+
+int lbm_get_populations(lbm_handle *h, double *f, double *g) {
+  if (!h) return LBM_EINVAL;
+  const int64_t nodes = (int64_t)h->cfg.nx * h->cfg.nr;
+  void *p;
+  int rc = h->scratch.get(NPOP * nodes * sizeof(float), &p);
+  if (rc) return rc;
+  if ((rc = launch_decode(h->prec, h->stream, h->d_desc, &h->cfg, h->step, (float *)p)))
+    return rc;
+  const int st = sync_and_check(h);
+  if (st == LBM_EDEVICE) return st;
+  std::vector<float> v((size_t)(NPOP * nodes));
+  LBM_HIP(hipMemcpy(v.data(), p, v.size() * sizeof(float), hipMemcpyDeviceToHost));
+  for (int64_t q = 0; q < 9 * nodes; ++q)
+    if (f) f[q] = v[q];
+  for (int64_t q = 0; q < 4 * nodes; ++q)
+    if (g) g[q] = v[9 * nodes + q];
+  return st;
+}
+
+int lbm_set_populations(lbm_handle *h, const double *f, const double *g, int64_t step) {
+  if (!h || !f || !g || step < 0) return LBM_EINVAL;
+  const int64_t nodes = (int64_t)h->cfg.nx * h->cfg.nr;
+  std::vector<float> v((size_t)(NPOP * nodes));
+  for (int64_t q = 0; q < 9 * nodes; ++q) {
+    if (!std::isfinite(f[q])) return LBM_EINVAL;
+    v[q] = (float)f[q];
+  }
+  for (int64_t q = 0; q < 4 * nodes; ++q) {
+    if (!std::isfinite(g[q])) return LBM_EINVAL;
+    v[9 * nodes + q] = (float)g[q];
+  }
+  void *p;
+  int rc = h->scratch.get(v.size() * sizeof(float), &p);
+  if (rc) return rc;
+  LBM_HIP(hipStreamSynchronize(h->stream));
+  LBM_HIP(hipMemcpy(p, v.data(), v.size() * sizeof(float), hipMemcpyHostToDevice));
+  h->step = step;
+  h->base = step;
+  if ((rc = upload_desc(h))) return rc;
+  if ((rc = launch_encode(h->prec, h->stream, h->d_desc, &h->cfg, step, (const float *)p)))
+    return rc;
+  LBM_HIP(hipStreamSynchronize(h->stream));
+  return clear_flag(h);
+}
+
+const char *lbm_strerror(int code) {
+  switch (code) {
+    case LBM_OK: return "ok";
+    case LBM_EINVAL: return "invalid argument or configuration";
+    case LBM_ENOMEM: return "out of memory or budget";
+    case LBM_EUNSTABLE: return "unstable: non-finite value or non-positive density";
+    case LBM_EDEVICE: return "HIP runtime error";
+    case LBM_ESTATE: return "call not valid in the current state";
+    default: return "unknown error";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,423 @@
+// lbm_batch.hip -- many resident jets advanced by one persistent launch per
+// step.  Population buffers are carved out of one device arena (the HBM
+// budget) by a first-fit allocator; every active jet has a descriptor, and
+// the step kernel walks a flat tile list covering all of them.  The launch
+// configuration (grid, kernel arguments) never changes with the set of
+// jets, so a captured graph of k steps is replayed as jets come and go.
+#include <algorithm>
+#include <map>
+#include <tuple>
+
+#include "lbm_runtime.hpp"
+
+using namespace lbmx;
+
+namespace {
+
+struct Slot {
+  bool used = false;
+  lbm_config cfg{};
+  std::vector<double> nu_tab, al_tab;
+  JetDesc desc{};
+  size_t off = 0, bytes = 0;
+  float4 *d_table = nullptr;
+  float4 *d_inlet = nullptr;
+  int64_t step = 0, target = 0;
+};
+
+// First-fit free list over [0, size) with 256-byte granules.
+struct Arena {
+  std::map<size_t, size_t> free_;  // offset -> size
+  void reset(size_t size) {
+    free_.clear();
+    if (size) free_[0] = size;
+  }
+  bool alloc(size_t bytes, size_t *off) {
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= bytes) {
+        *off = it->first;
+        const size_t rest = it->second - bytes, noff = it->first + bytes;
+        free_.erase(it);
+        if (rest) free_[noff] = rest;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    auto it = free_.emplace(off, bytes).first;
+    auto next = std::next(it);
+    if (next != free_.end() && it->first + it->second == next->first) {
+      it->second += next->second;
+      free_.erase(next);
+    }
+    if (it != free_.begin()) {
+      auto prev = std::prev(it);
+      if (prev->first + prev->second == it->first) {
+        prev->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+};
+
+}  // namespace
+
+struct lbm_batch {
+  int device = 0;
+  int prec = LBM_PREC_FP32;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  size_t budget = 0, used = 0;
+  void *arena_mem = nullptr;
+  Arena arena;
+  std::vector<Slot> slots;
+  JetDesc *d_jets = nullptr;     // compact list of active jets
+  JetDesc *d_slot_desc = nullptr;  // per slot, for the single-jet helper kernels
+  int32_t *d_tiles = nullptr;
+  BatchHdr *d_hdr = nullptr;
+  int32_t *d_flags = nullptr;
+  Scratch scratch;
+  std::vector<int32_t> active;  // slots in the compact list, in order
+  bool dirty = true;
+  int shape = -1;       // -1: auto
+  int32_t wg = 0;       // 0: auto
+  int32_t grid = 0;
+  std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;  // (k, shape, grid)
+};
+
+namespace {
+
+int pick_shape(const lbm_batch *b) { return b->shape >= 0 ? b->shape : default_tile_shape(); }
+
+void drop_graphs(lbm_batch *b) {
+  for (auto &kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+  b->graphs.clear();
+}
+
+// Rebuild and upload the compact jet list and tile prefix sums.
+int rebuild(lbm_batch *b) {
+  const int shape = pick_shape(b);
+  std::vector<JetDesc> jets;
+  std::vector<int32_t> start(1, 0);
+  b->active.clear();
+  for (int32_t s = 0; s < (int32_t)b->slots.size(); ++s) {
+    Slot &sl = b->slots[s];
+    if (!sl.used || sl.step >= sl.target) continue;
+    int32_t tx;
+    const int nt = tiles_of(&sl.cfg, shape, &tx);
+    sl.desc.tiles_x = tx;
+    sl.desc.step0 = sl.step;
+    jets.push_back(sl.desc);
+    start.push_back(start.back() + nt);
+    b->active.push_back(s);
+  }
+  const int32_t n = (int32_t)jets.size();
+  BatchHdr hdr{n, {0, 0, 0}};
+  LBM_HIP(hipStreamSynchronize(b->stream));
+  if (n) LBM_HIP(hipMemcpy(b->d_jets, jets.data(), n * sizeof(JetDesc), hipMemcpyHostToDevice));
+  LBM_HIP(hipMemcpy(b->d_tiles, start.data(), start.size() * sizeof(int32_t),
+                    hipMemcpyHostToDevice));
+  LBM_HIP(hipMemcpy(b->d_hdr, &hdr, sizeof hdr, hipMemcpyHostToDevice));
+  // persistent grid: enough workgroups to fill the chip several times over
+  int32_t g = b->wg > 0 ? b->wg : 2048;
+  g = (g + 7) / 8 * 8;
+  b->grid = g;
+  b->dirty = false;
+  return LBM_OK;
+}
+
+int run_group(lbm_batch *b, int32_t k) {
+  const int shape = pick_shape(b);
+  auto key = std::make_tuple((int)k, shape, (int)b->grid);
+  auto it = b->graphs.find(key);
+  if (it == b->graphs.end()) {
+    hipGraph_t g;
+    LBM_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    int rc = LBM_OK;
+    for (int32_t q = 0; q < k && !rc; ++q)
+      rc = launch_step(shape, b->prec, b->grid, b->stream, b->d_jets, b->d_tiles, b->d_hdr, q,
+                       b->d_flags);
+    if (!rc) rc = launch_advance(b->stream, b->d_jets, b->d_hdr, (int32_t)b->slots.size(), k);
+    const hipError_t e = hipStreamEndCapture(b->stream, &g);
+    if (rc || e != hipSuccess) return rc ? rc : LBM_EDEVICE;
+    hipGraphExec_t ex;
+    const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) return LBM_EDEVICE;
+    it = b->graphs.emplace(key, ex).first;
+  }
+  LBM_HIP(hipGraphLaunch(it->second, b->stream));
+  return LBM_OK;
+}
+
+Slot *slot_of(lbm_batch *b, int32_t s) {
+  if (!b || s < 0 || s >= (int32_t)b->slots.size() || !b->slots[s].used) return nullptr;
+  return &b->slots[s];
+}
+
+}  // namespace
+
+extern "C" {
+
+int lbm_batch_create(size_t budget_bytes, int32_t max_slots, int32_t precision,
+                     void *hip_stream, lbm_batch **out) {
+  if (!out) return LBM_EINVAL;
+  *out = nullptr;
+  if (max_slots < 1 || max_slots > 65536 || budget_bytes < 256) return LBM_EINVAL;
+  if (precision != LBM_PREC_FP32 && precision != LBM_PREC_FP16DEV &&
+      precision != LBM_PREC_BF16DEV)
+    return LBM_EINVAL;
+  lbm_batch *b = new (std::nothrow) lbm_batch();
+  if (!b) return LBM_ENOMEM;
+  b->prec = precision;
+  b->budget = budget_bytes & ~size_t(255);
+  b->slots.resize(max_slots);
+  (void)hipGetDevice(&b->device);
+  bool ok = hipMalloc(&b->arena_mem, b->budget) == hipSuccess &&
+            hipMalloc(&b->d_jets, max_slots * sizeof(JetDesc)) == hipSuccess &&
+            hipMalloc(&b->d_slot_desc, max_slots * sizeof(JetDesc)) == hipSuccess &&
+            hipMalloc(&b->d_tiles, (max_slots + 1) * sizeof(int32_t)) == hipSuccess &&
+            hipMalloc(&b->d_hdr, sizeof(BatchHdr)) == hipSuccess &&
+            hipMalloc(&b->d_flags, max_slots * sizeof(int32_t)) == hipSuccess;
+  if (ok && hip_stream) {
+    b->stream = (hipStream_t)hip_stream;
+  } else if (ok) {
+    ok = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) == hipSuccess;
+    b->own_stream = ok;
+  }
+  if (ok) {
+    std::vector<int32_t> zeros(max_slots, 0);
+    ok = hipMemcpy(b->d_flags, zeros.data(), max_slots * sizeof(int32_t),
+                   hipMemcpyHostToDevice) == hipSuccess;
+  }
+  if (!ok) {
+    lbm_batch_destroy(b);
+    return LBM_ENOMEM;
+  }
+  b->arena.reset(b->budget);
+  *out = b;
+  return LBM_OK;
+}
+
+int lbm_batch_jet_bytes(const lbm_batch *b, const lbm_config *cfg, size_t *bytes) {
+  if (!b || !cfg || !bytes) return LBM_EINVAL;
+  const int rc = validate_config(cfg, false);
+  if (rc) return rc;
+  *bytes = 2 * buffer_bytes(cfg, b->prec);
+  return LBM_OK;
+}
+
+int lbm_batch_admit(lbm_batch *b, const lbm_config *cfg, int32_t n_t, const double *ux,
+                    const double *ur, const double *T, int64_t target_steps, int32_t *slot) {
+  if (!b || !cfg || !slot || target_steps < 0) return LBM_EINVAL;
+  *slot = -1;
+  int rc = validate_config(cfg, false);
+  if (rc) return rc;
+  int32_t s = -1;
+  for (int32_t q = 0; q < (int32_t)b->slots.size(); ++q)
+    if (!b->slots[q].used) {
+      s = q;
+      break;
+    }
+  if (s < 0) return LBM_ENOMEM;
+  const size_t one = buffer_bytes(cfg, b->prec);
+  size_t off;
+  if (!b->arena.alloc(2 * one, &off)) return LBM_ENOMEM;
+  Slot &sl = b->slots[s];
+  sl = Slot();
+  sl.cfg = *cfg;
+  sl.cfg.precision = b->prec;
+  if (cfg->table_n > 0) {
+    sl.nu_tab.assign(cfg->nu_mult, cfg->nu_mult + cfg->table_n);
+    sl.al_tab.assign(cfg->alpha_mult, cfg->alpha_mult + cfg->table_n);
+    sl.cfg.nu_mult = sl.nu_tab.data();
+    sl.cfg.alpha_mult = sl.al_tab.data();
+  }
+  std::vector<float4> rows;
+  if ((rc = make_inlet(&sl.cfg, n_t, ux, ur, T, rows))) {
+    b->arena.release(off, 2 * one);
+    return rc;
+  }
+  std::vector<float4> table = make_table(&sl.cfg);
+  bool ok = hipMalloc(&sl.d_table, table.size() * sizeof(float4)) == hipSuccess &&
+            hipMalloc(&sl.d_inlet, rows.size() * sizeof(float4)) == hipSuccess;
+  ok = ok && hipMemcpy(sl.d_table, table.data(), table.size() * sizeof(float4),
+                       hipMemcpyHostToDevice) == hipSuccess &&
+       hipMemcpy(sl.d_inlet, rows.data(), rows.size() * sizeof(float4),
+                 hipMemcpyHostToDevice) == hipSuccess;
+  if (!ok) {
+    if (sl.d_table) (void)hipFree(sl.d_table);
+    if (sl.d_inlet) (void)hipFree(sl.d_inlet);
+    b->arena.release(off, 2 * one);
+    sl = Slot();
+    return LBM_ENOMEM;
+  }
+  sl.used = true;
+  sl.off = off;
+  sl.bytes = 2 * one;
+  sl.step = 0;
+  sl.target = target_steps;
+  JetDesc &d = sl.desc;
+  fill_desc(d, &sl.cfg);
+  d.buf[0] = (char *)b->arena_mem + off;
+  d.buf[1] = (char *)b->arena_mem + off + one;
+  d.table = sl.d_table;
+  d.inlet = sl.d_inlet;
+  d.n_t = n_t == 0 ? 1 : n_t;
+  d.target = target_steps;
+  d.step0 = 0;
+  d.slot = s;
+  int32_t tx;
+  tiles_of(&sl.cfg, pick_shape(b), &tx);
+  d.tiles_x = tx;
+  const int32_t zero = 0;
+  LBM_HIP(hipStreamSynchronize(b->stream));
+  LBM_HIP(hipMemcpy(b->d_slot_desc + s, &d, sizeof(JetDesc), hipMemcpyHostToDevice));
+  LBM_HIP(hipMemcpy(b->d_flags + s, &zero, sizeof zero, hipMemcpyHostToDevice));
+  rc = launch_init(b->prec, b->stream, b->d_slot_desc + s, &sl.cfg, 0, nullptr,
+                   make_float4((float)cfg->rho0, (float)cfg->ux0, (float)cfg->ur0,
+                               (float)cfg->T0));
+  if (rc) return rc;
+  b->used += sl.bytes;
+  b->dirty = true;
+  *slot = s;
+  return LBM_OK;
+}
+
+int lbm_batch_run(lbm_batch *b, int32_t k_steps) {
+  if (!b || k_steps < 0) return LBM_EINVAL;
+  if (k_steps == 0) return LBM_OK;
+  int rc;
+  if (b->dirty && (rc = rebuild(b))) return rc;
+  if (b->active.empty()) return LBM_OK;
+  if ((rc = run_group(b, k_steps))) return rc;
+  bool finished = false;
+  for (int32_t s : b->active) {
+    Slot &sl = b->slots[s];
+    sl.step = std::min<int64_t>(sl.step + k_steps, sl.target);
+    finished = finished || sl.step >= sl.target;
+  }
+  if (finished) b->dirty = true;  // drop finished jets from the tile list
+  return LBM_OK;
+}
+
+int lbm_batch_poll(lbm_batch *b, int32_t slot, int64_t *steps_done) {
+  Slot *sl = slot_of(b, slot);
+  if (!sl || !steps_done) return LBM_EINVAL;
+  *steps_done = sl->step;
+  return LBM_OK;
+}
+
+static int slot_flag(lbm_batch *b, int32_t slot, int32_t *flag) {
+  LBM_HIP(hipStreamSynchronize(b->stream));
+  LBM_HIP(hipGetLastError());
+  LBM_HIP(hipMemcpy(flag, b->d_flags + slot, sizeof(int32_t), hipMemcpyDeviceToHost));
+  return LBM_OK;
+}
+
+int lbm_batch_profiles(lbm_batch *b, int32_t slot, double *ux_axis, double *T_axis,
+                       double *ux_exit, double *T_exit) {
+  Slot *sl = slot_of(b, slot);
+  if (!sl) return LBM_EINVAL;
+  const int n = sl->cfg.nx + sl->cfg.nr;
+  void *p;
+  int rc = b->scratch.get(n * sizeof(float2), &p);
+  if (rc) return rc;
+  if ((rc = launch_profiles(b->prec, b->stream, b->d_slot_desc + slot, &sl->cfg, sl->step,
+                            (float2 *)p)))
+    return rc;
+  int32_t flag;
+  if ((rc = slot_flag(b, slot, &flag))) return rc;
+  std::vector<float2> v(n);
+  LBM_HIP(hipMemcpy(v.data(), p, n * sizeof(float2), hipMemcpyDeviceToHost));
+  for (int i = 0; i < sl->cfg.nx; ++i) {
+    if (ux_axis) ux_axis[i] = v[i].x;
+    if (T_axis) T_axis[i] = v[i].y;
+  }
+  for (int j = 0; j < sl->cfg.nr; ++j) {
+    if (ux_exit) ux_exit[j] = v[sl->cfg.nx + j].x;
+    if (T_exit) T_exit[j] = v[sl->cfg.nx + j].y;
+  }
+  return flag ? LBM_EUNSTABLE : LBM_OK;
+}
+
+int lbm_batch_moments(lbm_batch *b, int32_t slot, double *rho, double *ux, double *ur,
+                      double *T) {
+  Slot *sl = slot_of(b, slot);
+  if (!sl) return LBM_EINVAL;
+  const int64_t nodes = (int64_t)sl->cfg.nx * sl->cfg.nr;
+  void *p;
+  int rc = b->scratch.get(nodes * sizeof(float4), &p);
+  if (rc) return rc;
+  if ((rc = launch_moments(b->prec, b->stream, b->d_slot_desc + slot, &sl->cfg, sl->step,
+                           (float4 *)p)))
+    return rc;
+  int32_t flag;
+  if ((rc = slot_flag(b, slot, &flag))) return rc;
+  std::vector<float4> m((size_t)nodes);
+  LBM_HIP(hipMemcpy(m.data(), p, nodes * sizeof(float4), hipMemcpyDeviceToHost));
+  for (int64_t n = 0; n < nodes; ++n) {
+    if (rho) rho[n] = m[n].x;
+    if (ux) ux[n] = m[n].y;
+    if (ur) ur[n] = m[n].z;
+    if (T) T[n] = m[n].w;
+  }
+  return flag ? LBM_EUNSTABLE : LBM_OK;
+}
+
+int lbm_batch_retire(lbm_batch *b, int32_t slot) {
+  Slot *sl = slot_of(b, slot);
+  if (!sl) return LBM_EINVAL;
+  LBM_HIP(hipStreamSynchronize(b->stream));
+  b->arena.release(sl->off, sl->bytes);
+  b->used -= sl->bytes;
+  if (sl->d_table) (void)hipFree(sl->d_table);
+  if (sl->d_inlet) (void)hipFree(sl->d_inlet);
+  *sl = Slot();
+  b->dirty = true;
+  return LBM_OK;
+}
+
+int lbm_batch_active(const lbm_batch *b, int32_t *n_active, size_t *bytes_used) {
+  if (!b) return LBM_EINVAL;
+  int32_t n = 0;
+  for (const Slot &s : b->slots) n += s.used ? 1 : 0;
+  if (n_active) *n_active = n;
+  if (bytes_used) *bytes_used = b->used;
+  return LBM_OK;
+}
+
+int lbm_batch_set_launch(lbm_batch *b, int32_t tile_shape, int32_t workgroups) {
+  if (!b || workgroups < 0) return LBM_EINVAL;
+  int n;
+  tile_shapes(&n);
+  if (tile_shape < -1 || tile_shape >= n) return LBM_EINVAL;
+  LBM_HIP(hipStreamSynchronize(b->stream));
+  b->shape = tile_shape;
+  b->wg = workgroups;
+  b->dirty = true;
+  drop_graphs(b);
+  return LBM_OK;
+}
+
+void lbm_batch_destroy(lbm_batch *b) {
+  if (!b) return;
+  if (b->stream) (void)hipStreamSynchronize(b->stream);
+  drop_graphs(b);
+  for (Slot &s : b->slots) {
+    if (s.d_table) (void)hipFree(s.d_table);
+    if (s.d_inlet) (void)hipFree(s.d_inlet);
+  }
+  b->scratch.release();
+  if (b->arena_mem) (void)hipFree(b->arena_mem);
+  if (b->d_jets) (void)hipFree(b->d_jets);
+  if (b->d_slot_desc) (void)hipFree(b->d_slot_desc);
+  if (b->d_tiles) (void)hipFree(b->d_tiles);
+  if (b->d_hdr) (void)hipFree(b->d_hdr);
+  if (b->d_flags) (void)hipFree(b->d_flags);
+  if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+  delete b;
+}
+
+}  // extern "C"

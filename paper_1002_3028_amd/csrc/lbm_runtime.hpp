@@ -1,0 +1,97 @@
+// lbm_runtime.hpp -- host-side pieces shared by the single-jet and batch
+// runtimes: validation, descriptor setup, kernel tables, small helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "lbm_device.hpp"
+
+namespace lbmx {
+
+#define LBM_HIP(expr)                              \
+  do {                                             \
+    if ((expr) != hipSuccess) return LBM_EDEVICE;  \
+  } while (0)
+
+constexpr int64_t NO_TARGET = INT64_MAX / 4;
+constexpr int32_t ROW_ALIGN = 64;  // elements; keeps every row 128 B+ aligned
+
+inline int storage_bytes(int prec) { return prec == LBM_PREC_FP32 ? 4 : 2; }
+inline int32_t pitch_of(int32_t nx) { return (nx + ROW_ALIGN - 1) / ROW_ALIGN * ROW_ALIGN; }
+inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Bytes of one population buffer (13 planes).
+inline size_t buffer_bytes(const lbm_config *c, int prec) {
+  return align256((size_t)NPOP * (size_t)pitch_of(c->nx) * (size_t)c->nr * storage_bytes(prec));
+}
+
+int validate_config(const lbm_config *c, bool check_precision);
+
+// Host copy of the property tables as (M, dM) pairs at each grid point.
+std::vector<float4> make_table(const lbm_config *c);
+
+// Fill the physics fields of a descriptor (no buffers, table or inlet).
+void fill_desc(JetDesc &d, const lbm_config *c);
+
+// Inlet rows as float4 (ux, ur, T, 0); n_t == 0 gives one ambient row.
+int make_inlet(const lbm_config *c, int32_t n_t, const double *ux, const double *ur,
+               const double *T, std::vector<float4> &out);
+
+// ---- kernel tables ---------------------------------------------------------
+struct TileShape {
+  int bx, by, ny;
+  const void *fn[3];  // FP32, FP16-dev, BF16-dev
+};
+const TileShape *tile_shapes(int *count);
+int default_tile_shape();
+
+inline int codec_index(int prec) { return prec - LBM_PREC_FP32; }
+
+int launch_step(int shape, int prec, int grid, hipStream_t st, const JetDesc *jets,
+                const int32_t *tiles, const BatchHdr *hdr, int32_t koff, int32_t *flags);
+int launch_advance(hipStream_t st, JetDesc *jets, const BatchHdr *hdr, int32_t njets_max,
+                   int32_t delta);
+int launch_init(int prec, hipStream_t st, const JetDesc *d, const lbm_config *c, int64_t step,
+                const float4 *state, float4 u0);
+int launch_moments(int prec, hipStream_t st, const JetDesc *d, const lbm_config *c,
+                   int64_t step, float4 *out);
+int launch_profiles(int prec, hipStream_t st, const JetDesc *d, const lbm_config *c,
+                    int64_t step, float2 *out);
+int launch_conservation(int prec, hipStream_t st, const JetDesc *d, int64_t nodes, int64_t step,
+                        RedPartial *partial, int nblocks, RedPartial *out);
+int launch_decode(int prec, hipStream_t st, const JetDesc *d, const lbm_config *c, int64_t step,
+                  float *out);
+int launch_encode(int prec, hipStream_t st, const JetDesc *d, const lbm_config *c, int64_t step,
+                  const float *in);
+
+int tiles_of(const lbm_config *c, int shape, int32_t *tiles_x);
+
+// Simple device scratch that grows on demand.
+struct Scratch {
+  void *p = nullptr;
+  size_t bytes = 0;
+  int get(size_t need, void **out) {
+    if (need > bytes) {
+      if (p) (void)hipFree(p);
+      p = nullptr;
+      bytes = 0;
+      if (hipMalloc(&p, need) != hipSuccess) return LBM_ENOMEM;
+      bytes = need;
+    }
+    *out = p;
+    return LBM_OK;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+};
+
+}  // namespace lbmx

@@ -1,0 +1,95 @@
+"""Host-side checks of the HIP library that need no GPU: it loads, exports
+every entry point include/lbm.h declares, and rejects invalid configurations
+before touching the device."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1002_3028_amd import lbm
+    if not os.path.exists(lbm.LIB_PATH):
+        from paper_1002_3028_amd import build
+        build.build()
+    return lbm.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert len(names) >= 30
+    from paper_1002_3028_amd import lbm
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in lbm.exported_names(), n
+
+
+def test_tile_shapes_listed(lib):
+    from paper_1002_3028_amd import lbm
+    shapes = lbm.tile_shapes()
+    assert len(shapes) >= 4
+    for bx, by, ny in shapes:
+        assert bx % 64 == 0 and bx * by <= 1024 and ny >= 1
+
+
+def _params(**kw):
+    from paper_1002_3028_amd import inputs
+    p = inputs.jet_params(64, 16, cs=0.1, table_seed=0)
+    p.update(kw)
+    return p
+
+
+@pytest.mark.parametrize("bad", [
+    dict(tau_nu=0.5), dict(tau_alpha=0.4), dict(pr_t=0.0), dict(nx=1), dict(nr=1),
+    dict(r0=1.0),  # an axis must sit at r = 0
+    dict(bc=("periodic", "outflow", "axis", "freeslip")),
+    dict(bc=("inlet", "outflow", "freeslip", "axis")),
+    dict(cs=-0.1), dict(hoop=2), dict(rho0=0.0), dict(T0=math.nan),
+])
+def test_invalid_configs_rejected(lib, bad):
+    from paper_1002_3028_amd import lbm
+    cfg, keep = lbm.make_config(_params(**bad))
+    n = ctypes.c_size_t()
+    assert lib.lbm_bytes_required(ctypes.byref(cfg), ctypes.byref(n)) == lbm.EINVAL
+    h = ctypes.c_void_p(1)
+    assert lib.lbm_create(ctypes.byref(cfg), ctypes.byref(h)) == lbm.EINVAL
+    assert not h.value
+
+
+def test_precision_validated(lib):
+    from paper_1002_3028_amd import lbm
+    cfg, keep = lbm.make_config(_params(), precision=0)  # FP64 is the checker's, not ours
+    n = ctypes.c_size_t()
+    assert lib.lbm_bytes_required(ctypes.byref(cfg), ctypes.byref(n)) == lbm.EINVAL
+
+
+def test_bytes_required(lib):
+    from paper_1002_3028_amd import lbm
+    p = _params(nx=100, nr=30)
+    pitch = 128  # rows padded to 64 elements
+    assert lbm.bytes_required(p, "fp32") == 2 * ((13 * pitch * 30 * 4 + 255) // 256 * 256)
+    assert lbm.bytes_required(p, "fp16") == 2 * ((13 * pitch * 30 * 2 + 255) // 256 * 256)
+
+
+def test_strerror(lib):
+    from paper_1002_3028_amd import lbm
+    assert "unstable" in lbm.strerror(lbm.EUNSTABLE)
+    assert lbm.strerror(12345) == "unknown error"
+
+
+def test_null_safety(lib):
+    lib.lbm_destroy(None)
+    lib.lbm_batch_destroy(None)
+    assert lib.lbm_step_count(None) == -1
+    assert lib.lbm_step(None, 1) == -1
