@@ -213,10 +213,11 @@ static double bounce(const lbm_ref_handle *h, int P, int k, int i, int j, int si
   return v;
 }
 
-/* x-side rule for population k taken from column ip of row jr; i_land is the
- * column of the node that receives it. */
+/* x-side rule for population k taken from column ip of row jr; (i_land,
+ * j_land) is the node that receives it (the pulling node, or for a mirrored
+ * pull the node of the edge row). */
 static double pull_x(const lbm_ref_handle *h, int P, int k, int ip, int jr,
-                     int i_land) {
+                     int i_land, int j_land) {
   const lbm_ref_config *c = &h->c;
   if (ip >= 0 && ip < c->nx) return stored(h, P, k, ip, jr);
   int side = ip < 0 ? SX0 : SX1;
@@ -231,7 +232,7 @@ static double pull_x(const lbm_ref_handle *h, int P, int k, int ip, int jr,
       return eq_link(P, k, 1.0, h->in_ux[row], h->in_ur[row], h->in_T[row]);
     }
     case LBM_REF_BC_WALL:
-      return bounce(h, P, k, i_land, jr, side);
+      return bounce(h, P, k, i_land, j_land, side);
     case LBM_REF_BC_EQ: {
       const double *e = c->eq_state[side];
       return eq_link(P, k, e[0], e[1], e[2], e[3]);
@@ -245,14 +246,14 @@ static double pull(const lbm_ref_handle *h, int P, int k, int i, int j) {
   int ex = (P == FLOW) ? EX9[k] : EX4[k];
   int er = (P == FLOW) ? ER9[k] : ER4[k];
   int ip = i - ex, jp = j - er;
-  if (jp >= 0 && jp < c->nr) return pull_x(h, P, k, ip, jp, i);
+  if (jp >= 0 && jp < c->nr) return pull_x(h, P, k, ip, jp, i, j);
   int side = jp < 0 ? SR0 : SR1;
   int jedge = jp < 0 ? 0 : c->nr - 1;
   switch (c->bc[side]) {
     case LBM_REF_BC_AXIS:
     case LBM_REF_BC_FREESLIP: {
       int km = (P == FLOW) ? MIR9[k] : MIR4[k];
-      return pull_x(h, P, km, ip, jedge, i);
+      return pull_x(h, P, km, ip, jedge, i, jedge);
     }
     case LBM_REF_BC_WALL:
       return bounce(h, P, k, i, j, side);

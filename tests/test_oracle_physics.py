@@ -373,3 +373,25 @@ def test_x_translation_equivariance(ref):
         ma, mb = a.moments(), b.moments()
     for key in ma:
         np.testing.assert_array_equal(mb[key], np.roll(ma[key], 5, axis=1))
+
+
+def test_xr_transpose_equivariance_planar_walls(ref):
+    """Planar limit (r0 -> infinity, so the axisymmetric sources vanish) in a
+    square box with a wall on every side: swapping x and r (and u_x, u_r)
+    commutes with a step.  Pins the x-side wall rule to the same half-way
+    bounce-back as the r-side wall (diagonal links included), and the
+    thermal anti-bounce-back on both."""
+    n = 14
+    p = base(n, n, r0=1e12, bc=("wall", "wall", "wall", "wall"),
+             wall_T=[0.9, 0.2, 0.9, 0.2], tau_nu=0.7, tau_alpha=0.65, cs=0.15)
+    rho, ux, ur, T = inputs.perturbed_state(n, n, 21)
+    with ref.RefSolver(p) as a, ref.RefSolver(p) as b:
+        a.set_state(rho, ux, ur, T)
+        b.set_state(rho.T, ur.T, ux.T, T.T)
+        a.step(15)
+        b.step(15)
+        ma, mb = a.moments(), b.moments()
+    np.testing.assert_allclose(mb["rho"], ma["rho"].T, rtol=1e-11, atol=0)
+    np.testing.assert_allclose(mb["ux"], ma["ur"].T, rtol=0, atol=1e-11)
+    np.testing.assert_allclose(mb["ur"], ma["ux"].T, rtol=0, atol=1e-11)
+    np.testing.assert_allclose(mb["T"], ma["T"].T, rtol=0, atol=1e-11)
