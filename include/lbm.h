@@ -186,9 +186,10 @@ int lbm_batch_active(const lbm_batch *b, int32_t *n_active, size_t *bytes_used);
 int lbm_batch_set_launch(lbm_batch *b, int32_t tile_shape, int32_t workgroups);
 void lbm_batch_destroy(lbm_batch *b);
 
-/* Compiled tile shapes of the step kernel: count, and (bx, by, ny) of one. */
+/* Compiled tile shapes of the step kernel: count, and one shape: a workgroup
+ * of bx x by threads, each updating nx consecutive axial nodes in ny rows. */
 int lbm_tile_shape_count(void);
-int lbm_tile_shape(int32_t index, int32_t *bx, int32_t *by, int32_t *ny);
+int lbm_tile_shape(int32_t index, int32_t *bx, int32_t *by, int32_t *ny, int32_t *nx);
 int lbm_set_tile_shape(lbm_handle *h, int32_t index);
 
 #ifdef __cplusplus

@@ -113,7 +113,12 @@ int upload_inlet(lbm_handle *h, const std::vector<float4> &rows, int32_t n_t) {
   h->d_inlet = p;
   h->desc.inlet = p;
   h->desc.n_t = n_t;
-  return upload_desc(h);
+  int rc = upload_desc(h);
+  if (rc) return rc;
+  // the inlet ghosts of the current buffer follow the new rows
+  if ((rc = launch_ghost_fill(h->prec, h->stream, h->d_desc, &h->cfg, h->step))) return rc;
+  LBM_HIP(hipStreamSynchronize(h->stream));
+  return LBM_OK;
 }
 
 int create_common(const lbm_config *cfg, void *dev_buf, size_t bytes, void *stream,
@@ -189,8 +194,14 @@ int create_common(const lbm_config *cfg, void *dev_buf, size_t bytes, void *stre
     release(h);
     return rc;
   }
-  rc = launch_init(h->prec, h->stream, h->d_desc, &h->cfg, 0, nullptr,
-                   make_float4((float)cfg->rho0, (float)cfg->ux0, (float)cfg->ur0, (float)cfg->T0));
+  // both buffers at the initial equilibrium, each with its ghost ring (the
+  // constant ghosts of equilibrium sides are only ever written here)
+  const float4 u0 =
+      make_float4((float)cfg->rho0, (float)cfg->ux0, (float)cfg->ur0, (float)cfg->T0);
+  for (int64_t q = 1; q >= 0 && !rc; --q) {
+    rc = launch_init(h->prec, h->stream, h->d_desc, &h->cfg, q, nullptr, u0);
+    if (!rc) rc = launch_ghost_fill(h->prec, h->stream, h->d_desc, &h->cfg, q);
+  }
   if (rc || hipStreamSynchronize(h->stream) != hipSuccess) {
     release(h);
     return rc ? rc : LBM_EDEVICE;
@@ -404,6 +415,7 @@ int lbm_set_state(lbm_handle *h, const double *rho, const double *ux, const doub
   if ((rc = launch_init(h->prec, h->stream, h->d_desc, &h->cfg, h->step, (const float4 *)p,
                         make_float4(0, 0, 0, 0))))
     return rc;
+  if ((rc = launch_ghost_fill(h->prec, h->stream, h->d_desc, &h->cfg, h->step))) return rc;
   LBM_HIP(hipStreamSynchronize(h->stream));
   return clear_flag(h);
 }
@@ -449,6 +461,7 @@ int lbm_set_populations(lbm_handle *h, const double *f, const double *g, int64_t
   if ((rc = upload_desc(h))) return rc;
   if ((rc = launch_encode(h->prec, h->stream, h->d_desc, &h->cfg, step, (const float *)p)))
     return rc;
+  if ((rc = launch_ghost_fill(h->prec, h->stream, h->d_desc, &h->cfg, step))) return rc;
   LBM_HIP(hipStreamSynchronize(h->stream));
   return clear_flag(h);
 }

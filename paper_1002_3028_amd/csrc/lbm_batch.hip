@@ -275,9 +275,12 @@ int lbm_batch_admit(lbm_batch *b, const lbm_config *cfg, int32_t n_t, const doub
   LBM_HIP(hipStreamSynchronize(b->stream));
   LBM_HIP(hipMemcpy(b->d_slot_desc + s, &d, sizeof(JetDesc), hipMemcpyHostToDevice));
   LBM_HIP(hipMemcpy(b->d_flags + s, &zero, sizeof zero, hipMemcpyHostToDevice));
-  rc = launch_init(b->prec, b->stream, b->d_slot_desc + s, &sl.cfg, 0, nullptr,
-                   make_float4((float)cfg->rho0, (float)cfg->ux0, (float)cfg->ur0,
-                               (float)cfg->T0));
+  const float4 u0 =
+      make_float4((float)cfg->rho0, (float)cfg->ux0, (float)cfg->ur0, (float)cfg->T0);
+  for (int64_t q = 1; q >= 0 && !rc; --q) {
+    rc = launch_init(b->prec, b->stream, b->d_slot_desc + s, &sl.cfg, q, nullptr, u0);
+    if (!rc) rc = launch_ghost_fill(b->prec, b->stream, b->d_slot_desc + s, &sl.cfg, q);
+  }
   if (rc) return rc;
   b->used += sl.bytes;
   b->dirty = true;

@@ -20,6 +20,22 @@ namespace lbmx {
 // ---------------------------------------------------------------------------
 constexpr int NPOP = 13;
 
+// Storage layout of one population plane: (nr + 2) rows of `pitch` elements.
+// Node (i, j), i = -1..nx, j = -1..nr, sits at (j + 1) * pitch + XOFF + i:
+// row -1, row nr, column -1 and column nx form the ghost ring that holds the
+// values the edge nodes pull at the next step.  XOFF keeps interior rows
+// aligned; the row end leaves room for vector reads past column nx.
+constexpr int32_t XOFF = 64;
+__host__ __device__ inline int32_t layout_pitch(int32_t nx) {
+  return (XOFF + nx + 1 + 8 + 63) / 64 * 64;
+}
+__host__ __device__ inline int64_t layout_plane(int32_t nx, int32_t nr) {
+  return (int64_t)layout_pitch(nx) * (nr + 2);
+}
+__host__ __device__ inline int64_t node_index(int32_t pitch, int i, int j) {
+  return (int64_t)(j + 1) * pitch + XOFF + i;
+}
+
 __host__ __device__ constexpr int ex9(int k) {
   return (k == 1 || k == 5 || k == 8) ? 1 : (k == 3 || k == 6 || k == 7) ? -1 : 0;
 }
@@ -46,6 +62,20 @@ __host__ __device__ constexpr int per(int p) { return p < 9 ? er9(p) : er4(p - 9
 
 enum : int32_t { BC_INLET = 0, BC_OUTFLOW = 1, BC_PERIODIC = 2, BC_AXIS = 3,
                  BC_FREESLIP = 4, BC_WALL = 5, BC_EQ = 6 };
+
+// Pointers into device memory that the compiler must treat as global (not
+// flat) address space: the buffers are reached through the descriptor, so
+// their address space cannot be inferred.
+template <class T>
+using gptr = __attribute__((address_space(1))) T *;
+template <class T>
+__device__ __forceinline__ gptr<T> as_global(T *p) {
+  return (gptr<T>)p;
+}
+template <class T>
+__device__ __forceinline__ gptr<const T> as_global(const T *p) {
+  return (gptr<const T>)p;
+}
 
 // ---------------------------------------------------------------------------
 // Per-jet descriptor, read by every kernel through a device pointer.
@@ -149,28 +179,31 @@ __device__ __forceinline__ bool collide(const JetDesc &d, float rinv, float r2,
   const float irho = fast_rcp(rho);
   const float ux = mx * irho, ur = mr * irho;
 
-  // non-equilibrium parts
-  float fn[9];
+  // eq. (4): Q_ij = sum_k e_ki e_kj (f_k - f_k^eq).  The equilibrium is
+  // recomputed in the update below rather than kept, to hold fewer registers.
+  float qxx = 0.f, qrr = 0.f, qxr = 0.f;
 #pragma unroll
-  for (int k = 0; k < 9; ++k) fn[k] = f[k] - feq_link(k, rho, ux, ur);
-  float gn[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) gn[k] = g[k] - geq_link(k, T, ux, ur);
+  for (int k = 1; k < 9; ++k) {
+    const float fn = f[k] - feq_link(k, rho, ux, ur);
+    if (ex9(k) != 0) qxx += fn;
+    if (er9(k) != 0) qrr += fn;
+    if (ex9(k) * er9(k) != 0) qxr += (float)(ex9(k) * er9(k)) * fn;
+  }
+  // sum_k e_kr g_k^neq (the links +r and -r)
+  const float jr = (g[1] - geq_link(1, T, ux, ur)) - (g[3] - geq_link(3, T, ux, ur));
 
   // eq. (6): multiplier tables, linear on a uniform grid, clamped
   float x = fmaxf((T - d.t_lo) * d.t_scale, 0.0f);  // NaN -> 0
   x = fminf(x, (float)(d.table_n - 1));
   const int i0 = max(min((int)x, d.table_n - 2), 0);
   const float w = x - (float)i0;
-  const float4 te = d.table[i0];
+  const gptr<const float> tp = as_global((const float *)d.table) + 4 * i0;
+  const float4 te = make_float4(tp[0], tp[1], tp[2], tp[3]);
   const float nu = d.nu0 * (te.x + w * te.y);
   const float alpha = d.alpha0 * (te.z + w * te.w);
   const float tau_nu = 0.5f + 3.0f * nu;
 
-  // eq. (4): Q_ij and the local relaxation time
-  const float qxx = (fn[1] + fn[3]) + ((fn[5] + fn[6]) + (fn[7] + fn[8]));
-  const float qrr = (fn[2] + fn[4]) + ((fn[5] + fn[6]) + (fn[7] + fn[8]));
-  const float qxr = (fn[5] + fn[7]) - (fn[6] + fn[8]);
+  // eq. (4): local relaxation time
   const float qn = fast_sqrt(2.0f * (qxx * qxx + 2.0f * qxr * qxr + qrr * qrr));
   const float tau = 0.5f * (tau_nu + fast_sqrt(tau_nu * tau_nu + d.c18 * qn * irho));
   // eqs. (3), (5)
@@ -186,16 +219,17 @@ __device__ __forceinline__ bool collide(const JetDesc &d, float rinv, float r2,
   const float hden = d.hoop ? fast_rcp(r2 + 2.0f * nu_tot) : rinv * rinv;
   const float Fx = (-rho * ux * ur - kv * qxr) * rinv + rho * d.G;
   const float Fr = (-rho * ur * ur - kv * qrr) * rinv - 2.0f * rho * nu_tot * ur * hden;
-  const float S = (-T * ur - ka * (gn[1] - gn[3])) * rinv;
+  const float S = (-T * ur - ka * jr) * rinv;
 
   // eq. (1)
   const float fx6 = Fx * (1.0f / 6.0f), fr6 = Fr * (1.0f / 6.0f);
 #pragma unroll
   for (int k = 0; k < 9; ++k)
-    f[k] = f[k] - fn[k] * itau + w9(k) * theta + (float)ex9(k) * fx6 + (float)er9(k) * fr6;
+    f[k] = f[k] - (f[k] - feq_link(k, rho, ux, ur)) * itau + w9(k) * theta +
+           (float)ex9(k) * fx6 + (float)er9(k) * fr6;
   const float s4 = 0.25f * S;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) g[k] = g[k] - gn[k] * itau_a + s4;
+  for (int k = 0; k < 4; ++k) g[k] = g[k] - (g[k] - geq_link(k, T, ux, ur)) * itau_a + s4;
 
   return (rho > 0.0f) && (rho < __builtin_inff()) && (fabsf(T) < __builtin_inff());
 }
@@ -205,19 +239,29 @@ __device__ __forceinline__ bool collide(const JetDesc &d, float rinv, float r2,
 // ---------------------------------------------------------------------------
 template <class C>
 struct Src {
-  const typename C::T *__restrict__ base;
+  gptr<const typename C::T> base;
   int64_t plane;
   int32_t pitch;
   __device__ __forceinline__ float load(const JetDesc &d, int p, int i, int j) const {
-    return C::dec(base[(int64_t)p * plane + (int64_t)j * pitch + i], pop_offset<C>(d, p));
+    return C::dec(base[(int64_t)p * plane + node_index(pitch, i, j)], pop_offset<C>(d, p));
   }
 };
 
-// x-side rule for plane p taken from column ip of row jr; i_land is the
-// column of the receiving node.
+template <class C>
+struct Dst {
+  gptr<typename C::T> base;
+  int64_t plane;
+  int32_t pitch;
+  __device__ __forceinline__ void put(const JetDesc &d, int p, int i, int j, float v) const {
+    base[(int64_t)p * plane + node_index(pitch, i, j)] = C::enc(v, pop_offset<C>(d, p));
+  }
+};
+
+// x-side rule for plane p taken from column ip of row jr; (i_land, j_land)
+// is the receiving node (for a mirrored pull, the node of the edge row).
 template <class C>
 __device__ __forceinline__ float pull_x(const JetDesc &d, const Src<C> &s, int p, int ip,
-                                        int jr, int i_land, const float4 *inrow) {
+                                        int jr, int i_land, int j_land, const float4 *inrow) {
   if (ip >= 0 && ip < d.nx) return s.load(d, p, ip, jr);
   const int side = ip < 0 ? 0 : 1;
   switch (d.bc[side]) {
@@ -226,12 +270,13 @@ __device__ __forceinline__ float pull_x(const JetDesc &d, const Src<C> &s, int p
     case BC_OUTFLOW:
       return s.load(d, p, d.nx - 1, jr);
     case BC_INLET: {
-      const float4 q = inrow[jr];
+      const gptr<const float> qp = as_global((const float *)inrow) + 4 * jr;
+      const float4 q = make_float4(qp[0], qp[1], qp[2], qp[3]);
       return eq_plane(p, 1.0f, q.x, q.y, q.z);
     }
     case BC_WALL: {
       const int po = p < 9 ? opp9(p) : 9 + opp4(p - 9);
-      float v = s.load(d, po, i_land, jr);
+      float v = s.load(d, po, i_land, j_land);
       const float tw = d.wallT[side];
       if (p >= 9 && tw == tw) v = -v + 0.5f * tw;
       return v;
@@ -249,12 +294,13 @@ template <class C>
 __device__ __forceinline__ float pull_edge(const JetDesc &d, const Src<C> &s, int p, int i,
                                            int j, const float4 *inrow) {
   const int ip = i - pex(p), jp = j - per(p);
-  if (jp >= 0 && jp < d.nr) return pull_x<C>(d, s, p, ip, jp, i, inrow);
+  if (jp >= 0 && jp < d.nr) return pull_x<C>(d, s, p, ip, jp, i, j, inrow);
   const int side = jp < 0 ? 2 : 3;
   const int bc = d.bc[side];
   if (bc == BC_AXIS || bc == BC_FREESLIP) {
     const int pm = p < 9 ? mir9(p) : 9 + mir4(p - 9);
-    return pull_x<C>(d, s, pm, ip, jp < 0 ? 0 : d.nr - 1, i, inrow);
+    const int je = jp < 0 ? 0 : d.nr - 1;
+    return pull_x<C>(d, s, pm, ip, je, i, je, inrow);
   }
   if (bc == BC_WALL) {
     const int po = p < 9 ? opp9(p) : 9 + opp4(p - 9);
@@ -267,25 +313,125 @@ __device__ __forceinline__ float pull_edge(const JetDesc &d, const Src<C> &s, in
   return eq_plane(p, e[0], e[1], e[2], e[3]);
 }
 
-// All 13 pulled values of node (i, j); interior nodes take direct loads.
+// All 13 pulled values of node (i, j) from a buffer whose ghost ring is
+// current: every pull is a plain load.
 template <class C>
 __device__ __forceinline__ void pull_node(const JetDesc &d, const Src<C> &s, int i, int j,
-                                          const float4 *inrow, float (&f)[9], float (&g)[4]) {
-  const bool interior = (i >= 1) & (i <= d.nx - 2) & (j >= 1) & (j <= d.nr - 2);
-  if (interior) {
-    const typename C::T *b = s.base + (int64_t)j * s.pitch + i;
+                                          float (&f)[9], float (&g)[4]) {
 #pragma unroll
-    for (int p = 0; p < NPOP; ++p) {
-      const float v = C::dec(b[(int64_t)p * s.plane - (int64_t)per(p) * s.pitch - pex(p)],
-                             pop_offset<C>(d, p));
-      if (p < 9) f[p] = v; else g[p - 9] = v;
+  for (int p = 0; p < NPOP; ++p) {
+    const float v = s.load(d, p, i - pex(p), j - per(p));
+    if (p < 9) f[p] = v; else g[p - 9] = v;
+  }
+}
+
+// Thermal wall: anti-bounce-back towards the wall temperature, or plain
+// bounce-back (adiabatic) when it is NaN.
+__device__ __forceinline__ float wall_g(const JetDesc &d, int side, float v) {
+  const float tw = d.wallT[side];
+  return tw == tw ? -v + 0.5f * tw : v;
+}
+
+// After the collision of node (i, j), write the ghost values of the next
+// step that this node is the source of, following the edge rules (r side
+// first; a mirrored pull goes through the x rule at the edge row).  Ghosts
+// of equilibrium sides are constant and written once by the ghost fill.
+// `in` is the inlet row of the next step.
+template <class C>
+__device__ __forceinline__ void ghost_epilogue(const JetDesc &d, const Dst<C> &o, int i, int j,
+                                               const float (&f)[9], const float (&g)[4],
+                                               const float4 *in) {
+  const int nx = d.nx, nr = d.nr;
+  const int x0 = d.bc[0], x1 = d.bc[1], r0 = d.bc[2], r1 = d.bc[3];
+  const bool mir0 = (r0 == BC_AXIS) | (r0 == BC_FREESLIP);
+  const bool mir1 = r1 == BC_FREESLIP;
+  if (j == 0) {  // ghost row -1: links 2, 5, 6 and g1 (+r)
+    if (mir0) {
+      o.put(d, 2, i, -1, f[4]);
+      o.put(d, 5, i, -1, f[8]);
+      o.put(d, 6, i, -1, f[7]);
+      o.put(d, 10, i, -1, g[3]);
+    } else if (r0 == BC_WALL) {
+      o.put(d, 2, i, -1, f[4]);
+      o.put(d, 5, i - 1, -1, f[7]);
+      o.put(d, 6, i + 1, -1, f[8]);
+      o.put(d, 10, i, -1, wall_g(d, 2, g[3]));
     }
-  } else {
-#pragma unroll
-    for (int p = 0; p < NPOP; ++p) {
-      const float v = pull_edge<C>(d, s, p, i, j, inrow);
-      if (p < 9) f[p] = v; else g[p - 9] = v;
+  }
+  if (j == nr - 1) {  // ghost row nr: links 4, 7, 8 and g3 (-r)
+    if (mir1) {
+      o.put(d, 4, i, nr, f[2]);
+      o.put(d, 7, i, nr, f[6]);
+      o.put(d, 8, i, nr, f[5]);
+      o.put(d, 12, i, nr, g[1]);
+    } else if (r1 == BC_WALL) {
+      o.put(d, 4, i, nr, f[2]);
+      o.put(d, 7, i + 1, nr, f[5]);
+      o.put(d, 8, i - 1, nr, f[6]);
+      o.put(d, 12, i, nr, wall_g(d, 3, g[1]));
     }
+  }
+  if (i == 0) {  // ghost column -1 (rows 0..nr-1): links 1, 5, 8 and g0 (+x)
+    if (x0 == BC_INLET) {
+      const float4 q = in[j];
+      o.put(d, 1, -1, j, feq_link(1, 1.0f, q.x, q.y));
+      o.put(d, 5, -1, j, feq_link(5, 1.0f, q.x, q.y));
+      o.put(d, 8, -1, j, feq_link(8, 1.0f, q.x, q.y));
+      o.put(d, 9, -1, j, geq_link(0, q.z, q.x, q.y));
+    } else if (x0 == BC_WALL) {
+      o.put(d, 1, -1, j, f[3]);
+      if (j >= 1) o.put(d, 5, -1, j - 1, f[7]);
+      if (j + 1 < nr) o.put(d, 8, -1, j + 1, f[6]);
+      o.put(d, 9, -1, j, wall_g(d, 0, g[2]));
+    }
+    if (x1 == BC_PERIODIC) {  // column nx repeats column 0
+      o.put(d, 3, nx, j, f[3]);
+      o.put(d, 6, nx, j, f[6]);
+      o.put(d, 7, nx, j, f[7]);
+      o.put(d, 11, nx, j, g[2]);
+    }
+  }
+  if (i == nx - 1) {  // ghost column nx: links 3, 6, 7 and g2 (-x)
+    if (x1 == BC_OUTFLOW) {
+      o.put(d, 3, nx, j, f[3]);
+      o.put(d, 6, nx, j, f[6]);
+      o.put(d, 7, nx, j, f[7]);
+      o.put(d, 11, nx, j, g[2]);
+    } else if (x1 == BC_WALL) {
+      o.put(d, 3, nx, j, f[1]);
+      if (j >= 1) o.put(d, 6, nx, j - 1, f[8]);
+      if (j + 1 < nr) o.put(d, 7, nx, j + 1, f[5]);
+      o.put(d, 11, nx, j, wall_g(d, 1, g[0]));
+    }
+    if (x0 == BC_PERIODIC) {  // column -1 repeats column nx-1
+      o.put(d, 1, -1, j, f[1]);
+      o.put(d, 5, -1, j, f[5]);
+      o.put(d, 8, -1, j, f[8]);
+      o.put(d, 9, -1, j, g[0]);
+    }
+  }
+  // corner ghosts under a mirror edge: the mirrored link goes through the
+  // x rule at the edge row
+  if (j == 0 && mir0) {
+    // (-1, -1) link 5 <- x rule of link 8 at column -1, row 0
+    if (i == nx - 1 && x0 == BC_PERIODIC) o.put(d, 5, -1, -1, f[8]);
+    if (i == 0 && x0 == BC_INLET) o.put(d, 5, -1, -1, feq_link(8, 1.0f, in[0].x, in[0].y));
+    if (i == 0 && x0 == BC_WALL) o.put(d, 5, -1, -1, f[6]);
+    // (nx, -1) link 6 <- x rule of link 7 at column nx, row 0
+    if (i == 0 && x1 == BC_PERIODIC) o.put(d, 6, nx, -1, f[7]);
+    if (i == nx - 1 && x1 == BC_OUTFLOW) o.put(d, 6, nx, -1, f[7]);
+    if (i == nx - 1 && x1 == BC_WALL) o.put(d, 6, nx, -1, f[5]);
+  }
+  if (j == nr - 1 && mir1) {
+    // (-1, nr) link 8 <- x rule of link 5 at column -1, row nr-1
+    if (i == nx - 1 && x0 == BC_PERIODIC) o.put(d, 8, -1, nr, f[5]);
+    if (i == 0 && x0 == BC_INLET)
+      o.put(d, 8, -1, nr, feq_link(5, 1.0f, in[nr - 1].x, in[nr - 1].y));
+    if (i == 0 && x0 == BC_WALL) o.put(d, 8, -1, nr, f[7]);
+    // (nx, nr) link 7 <- x rule of link 6 at column nx, row nr-1
+    if (i == 0 && x1 == BC_PERIODIC) o.put(d, 7, nx, nr, f[6]);
+    if (i == nx - 1 && x1 == BC_OUTFLOW) o.put(d, 7, nx, nr, f[6]);
+    if (i == nx - 1 && x1 == BC_WALL) o.put(d, 7, nx, nr, f[8]);
   }
 }
 

@@ -19,7 +19,8 @@ static bool side_ok(int side, int bc) {
 int validate_config(const lbm_config *c, bool check_precision) {
   if (!c || c->abi_version != LBM_ABI_VERSION) return LBM_EINVAL;
   if (c->nx < 2 || c->nr < 2) return LBM_EINVAL;
-  if ((int64_t)pitch_of(c->nx) * c->nr > (int64_t)1 << 31) return LBM_EINVAL;
+  // every byte offset inside a buffer must fit the 32-bit buffer offsets
+  if ((int64_t)NPOP * layout_plane(c->nx, c->nr) * 4 >= ((int64_t)1 << 31)) return LBM_EINVAL;
   if (!(c->tau_nu > 0.5) || !(c->tau_alpha > 0.5) || !std::isfinite(c->tau_nu) ||
       !std::isfinite(c->tau_alpha))
     return LBM_EINVAL;
@@ -81,8 +82,8 @@ std::vector<float4> make_table(const lbm_config *c) {
 void fill_desc(JetDesc &d, const lbm_config *c) {
   d.nx = c->nx;
   d.nr = c->nr;
-  d.pitch = pitch_of(c->nx);
-  d.plane = (int64_t)d.pitch * c->nr;
+  d.pitch = layout_pitch(c->nx);
+  d.plane = layout_plane(c->nx, c->nr);
   d.table_n = c->table_n == 0 ? 2 : c->table_n;
   d.hoop = c->hoop;
   for (int s = 0; s < 4; ++s) {
@@ -122,16 +123,17 @@ int make_inlet(const lbm_config *c, int32_t n_t, const double *ux, const double 
 }
 
 // ---- tile shapes -------------------------------------------------------------
-#define LBM_SHAPE(BX, BY, NY)                                                   \
-  {BX, BY, NY,                                                                  \
-   {(const void *)&step_kernel<CodecF32, BX, BY, NY>,                           \
-    (const void *)&step_kernel<CodecF16, BX, BY, NY>,                           \
-    (const void *)&step_kernel<CodecBF16, BX, BY, NY>}}
+#define LBM_SHAPE(BX, BY, NY, NX, W)                                             \
+  {BX, BY, NY, NX, W,                                                            \
+   {(const void *)&step_kernel<CodecF32, BX, BY, NY, NX, W>,                     \
+    (const void *)&step_kernel<CodecF16, BX, BY, NY, NX, W>,                     \
+    (const void *)&step_kernel<CodecBF16, BX, BY, NY, NX, W>}}
 
 static const TileShape kShapes[] = {
-    LBM_SHAPE(64, 4, 1),  LBM_SHAPE(64, 4, 2),  LBM_SHAPE(64, 2, 4), LBM_SHAPE(128, 2, 2),
-    LBM_SHAPE(256, 1, 2), LBM_SHAPE(64, 8, 1),  LBM_SHAPE(256, 1, 4), LBM_SHAPE(128, 4, 1),
-    LBM_SHAPE(64, 1, 4),  LBM_SHAPE(128, 1, 2),
+    LBM_SHAPE(64, 4, 1, 1, 1),  LBM_SHAPE(128, 2, 1, 1, 1), LBM_SHAPE(256, 1, 1, 1, 1),
+    LBM_SHAPE(64, 8, 1, 1, 1),  LBM_SHAPE(64, 4, 2, 1, 1),  LBM_SHAPE(64, 4, 1, 2, 1),
+    LBM_SHAPE(128, 2, 1, 2, 1), LBM_SHAPE(256, 1, 1, 2, 1), LBM_SHAPE(64, 4, 1, 4, 1),
+    LBM_SHAPE(64, 2, 1, 4, 1),  LBM_SHAPE(64, 1, 1, 4, 1),  LBM_SHAPE(128, 1, 1, 2, 1),
 };
 #undef LBM_SHAPE
 
@@ -143,7 +145,7 @@ int default_tile_shape() { return 0; }
 
 int tiles_of(const lbm_config *c, int shape, int32_t *tiles_x) {
   const TileShape &s = kShapes[shape];
-  const int tx = (c->nx + s.bx - 1) / s.bx;
+  const int tx = (c->nx + s.bx * s.nx - 1) / (s.bx * s.nx);
   const int ty = (c->nr + s.by * s.ny - 1) / (s.by * s.ny);
   if (tiles_x) *tiles_x = tx;
   return tx * ty;
@@ -176,6 +178,20 @@ int launch_init(int prec, hipStream_t st, const JetDesc *d, const lbm_config *c,
   if (prec == LBM_PREC_FP32) init_t<CodecF32>(st, d, c, step, state, u0);
   else if (prec == LBM_PREC_FP16DEV) init_t<CodecF16>(st, d, c, step, state, u0);
   else init_t<CodecBF16>(st, d, c, step, state, u0);
+  LBM_HIP(hipGetLastError());
+  return LBM_OK;
+}
+
+template <class C>
+static void ghost_t(hipStream_t st, const JetDesc *d, const lbm_config *c, int64_t step) {
+  const int n = 2 * (c->nx + 2) + 2 * c->nr;
+  hipLaunchKernelGGL(ghost_fill_kernel<C>, dim3((n + 255) / 256), dim3(256), 0, st, d, step);
+}
+int launch_ghost_fill(int prec, hipStream_t st, const JetDesc *d, const lbm_config *c,
+                      int64_t step) {
+  if (prec == LBM_PREC_FP32) ghost_t<CodecF32>(st, d, c, step);
+  else if (prec == LBM_PREC_FP16DEV) ghost_t<CodecF16>(st, d, c, step);
+  else ghost_t<CodecBF16>(st, d, c, step);
   LBM_HIP(hipGetLastError());
   return LBM_OK;
 }
@@ -277,12 +293,14 @@ extern "C" int lbm_tile_shape_count(void) {
   return n;
 }
 
-extern "C" int lbm_tile_shape(int32_t index, int32_t *bx, int32_t *by, int32_t *ny) {
+extern "C" int lbm_tile_shape(int32_t index, int32_t *bx, int32_t *by, int32_t *ny,
+                              int32_t *nx) {
   int n;
   const lbmx::TileShape *s = lbmx::tile_shapes(&n);
-  if (index < 0 || index >= n || !bx || !by || !ny) return LBM_EINVAL;
+  if (index < 0 || index >= n || !bx || !by || !ny || !nx) return LBM_EINVAL;
   *bx = s[index].bx;
   *by = s[index].by;
   *ny = s[index].ny;
+  *nx = s[index].nx;
   return LBM_OK;
 }

@@ -5,21 +5,72 @@
 
 namespace lbmx {
 
+// Raw buffer access of B bytes per lane (buffer instructions: the base sits in
+// a scalar resource, one 32-bit VGPR offset is shared by all planes).
+constexpr int32_t BUF_WORD3 = 0x00020000;  // 32-bit data format, gfx9 family
+
+template <int B> struct Raw;
+template <> struct Raw<2> { typedef uint16_t type; };
+template <> struct Raw<4> { typedef uint32_t type; };
+template <> struct Raw<8> { typedef uint32_t type __attribute__((ext_vector_type(2))); };
+template <> struct Raw<16> { typedef uint32_t type __attribute__((ext_vector_type(4))); };
+
+template <int B>
+__device__ __forceinline__ typename Raw<B>::type buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                                          uint32_t soff) {
+  if constexpr (B == 2) return __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
+  else if constexpr (B == 4) return __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
+  else if constexpr (B == 8) return __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
+  else return __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+}
+template <int B>
+__device__ __forceinline__ void buf_store(typename Raw<B>::type v, __amdgpu_buffer_rsrc_t r,
+                                          uint32_t voff, uint32_t soff) {
+  if constexpr (B == 2) __builtin_amdgcn_raw_buffer_store_b16(v, r, voff, soff, 0);
+  else if constexpr (B == 4) __builtin_amdgcn_raw_buffer_store_b32(v, r, voff, soff, 0);
+  else if constexpr (B == 8) __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, soff, 0);
+  else __builtin_amdgcn_raw_buffer_store_b128(v, r, voff, soff, 0);
+}
+
+// NX elements of storage type T packed in one raw word
+template <class T, int NX>
+struct Pack {
+  typedef T vec __attribute__((ext_vector_type(NX)));
+};
+template <class T>
+struct Pack<T, 1> {
+  typedef T vec;
+};
+
+template <class T, int NX>
+__device__ __forceinline__ T elem(const typename Pack<T, NX>::vec &v, int e) {
+  if constexpr (NX == 1) return v;
+  else return v[e];
+}
+
 // ---------------------------------------------------------------------------
 // The fused collide-and-stream step over a flat tile list covering every
-// active jet.  A tile is BX x (BY * NY) nodes; thread (tx, ty) handles column
-// tile_x * BX + tx and rows tile_y * BY * NY + ty + q * BY, q < NY.
+// active jet.  A tile is (BX * NX) x (BY * NY) nodes: thread (tx, ty) handles
+// NX consecutive columns starting at (tile_x * BX + tx) * NX and rows
+// tile_y * BY * NY + ty + q * BY, q < NY.  The source buffer's ghost ring is
+// current, so every thread reads each plane with one buffer load of NX
+// elements and writes with one buffer store; edge nodes then write the
+// ghost values of the next step that they are the source of.
 // Workgroups walk the tile list with a grid stride; within each round the
 // tiles handed to one XCD (workgroup id mod 8) are contiguous, so the
-// neighbouring columns that the shifted pulls share stay in one L2.
+// columns that x-shifted pulls share with the neighbouring tile stay in one
+// L2.  W is the occupancy target (waves per SIMD) for register allocation.
 // The jet's state after s steps lives in buf[s & 1]; the step taken here is
 // step0 + koff, skipped once the jet reaches its target.
 // ---------------------------------------------------------------------------
-template <class C, int BX, int BY, int NY>
-__global__ __launch_bounds__(BX *BY) void step_kernel(const JetDesc *__restrict__ jets,
-                                                      const int32_t *__restrict__ tile_start,
-                                                      const BatchHdr *__restrict__ hdr,
-                                                      int32_t koff, int32_t *__restrict__ flags) {
+template <class C, int BX, int BY, int NY, int NX, int W>
+__global__ __launch_bounds__(BX *BY) __attribute__((amdgpu_waves_per_eu(W, 8))) void step_kernel(
+    const JetDesc *__restrict__ jets, const int32_t *__restrict__ tile_start,
+    const BatchHdr *__restrict__ hdr, int32_t koff, int32_t *__restrict__ flags) {
+  using T = typename C::T;
+  constexpr int ES = (int)sizeof(T);
+  constexpr int VB = ES * NX;  // bytes per lane per plane
+  using VT = typename Pack<T, NX>::vec;
   const int32_t njets = hdr->njets;
   const int32_t ntiles = tile_start[njets];
   const int32_t G = gridDim.x;  // a multiple of 8
@@ -41,25 +92,111 @@ __global__ __launch_bounds__(BX *BY) void step_kernel(const JetDesc *__restrict_
     const int32_t lt = t - tile_start[jid];
     const int32_t ty = lt / d.tiles_x;
     const int32_t tx = lt - ty * d.tiles_x;
-    const int i = tx * BX + (int)threadIdx.x;
-    Src<C> s{static_cast<const typename C::T *>(d.buf[step & 1]), d.plane, d.pitch};
-    typename C::T *__restrict__ dst = static_cast<typename C::T *>(d.buf[(step + 1) & 1]);
-    const float4 *inrow = d.inlet + (int64_t)(step % d.n_t) * d.nr;
+    const int i0 = (tx * BX + (int)threadIdx.x) * NX;
+    T *src_raw = static_cast<T *>(d.buf[step & 1]);
+    T *dst_raw = static_cast<T *>(d.buf[(step + 1) & 1]);
+    const uint32_t pitch_b = (uint32_t)d.pitch * ES, plane_b = (uint32_t)d.plane * ES;
+    const uint32_t span = (uint32_t)NPOP * plane_b;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(src_raw, 0, (int)span, BUF_WORD3);
+    const __amdgpu_buffer_rsrc_t rd = __builtin_amdgcn_make_buffer_rsrc(dst_raw, 0, (int)span, BUF_WORD3);
+    const int j_lo = ty * (BY * NY);
+    const bool tile_edge = (tx == 0) | ((tx + 1) * BX * NX >= d.nx) | (j_lo == 0) |
+                           (j_lo + BY * NY >= d.nr);
     bool ok = true;
 #pragma unroll
     for (int q = 0; q < NY; ++q) {
-      const int j = ty * (BY * NY) + (int)threadIdx.y + q * BY;
-      if (i >= d.nx || j >= d.nr) continue;
-      float f[9], g[4];
-      pull_node<C>(d, s, i, j, inrow, f, g);
-      const float r = d.r0 + (float)j + 0.5f;
-      ok &= collide(d, fast_rcp(r), r * r, f, g);
-      typename C::T *o = dst + (int64_t)j * d.pitch + i;
+      const int j = j_lo + (int)threadIdx.y + q * BY;
+      if (i0 >= d.nx || j >= d.nr) continue;
+      float f[NX][9], g[NX][4];
+      const uint32_t voff = (uint32_t)node_index(d.pitch, i0, j) * ES;
 #pragma unroll
-      for (int p = 0; p < NPOP; ++p)
-        o[(int64_t)p * d.plane] = C::enc(p < 9 ? f[p] : g[p - 9], pop_offset<C>(d, p));
+      for (int p = 0; p < NPOP; ++p) {
+        // pulled from node (i - e_x, j - e_r); the offset is never negative
+        // because plane p >= 1 starts at least a plane after the buffer
+        const uint32_t soff = (uint32_t)p * plane_b - (uint32_t)(per(p) * (int)pitch_b) -
+                              (uint32_t)(pex(p) * ES);
+        const VT v = __builtin_bit_cast(VT, buf_load<VB>(rs, voff, soff));
+        const float off = pop_offset<C>(d, p);
+#pragma unroll
+        for (int e = 0; e < NX; ++e) {
+          const float x = C::dec(elem<T, NX>(v, e), off);
+          if (p < 9) f[e][p] = x; else g[e][p - 9] = x;
+        }
+      }
+      const float r = d.r0 + (float)j + 0.5f;
+      const float rinv = fast_rcp(r), r2 = r * r;
+#pragma unroll
+      for (int e = 0; e < NX; ++e) {
+        const bool okn = collide(d, rinv, r2, f[e], g[e]);
+        ok &= okn | (i0 + e >= d.nx);
+      }
+      if (i0 + NX <= d.nx) {
+#pragma unroll
+        for (int p = 0; p < NPOP; ++p) {
+          const float off = pop_offset<C>(d, p);
+          VT v;
+#pragma unroll
+          for (int e = 0; e < NX; ++e) {
+            const T x = C::enc(p < 9 ? f[e][p] : g[e][p - 9], off);
+            if constexpr (NX == 1) v = x; else v[e] = x;
+          }
+          buf_store<VB>(__builtin_bit_cast(typename Raw<VB>::type, v), rd, voff,
+                        (uint32_t)p * plane_b);
+        }
+      } else {
+        const gptr<T> o = as_global(dst_raw) + node_index(d.pitch, i0, j);
+#pragma unroll
+        for (int e = 0; e < NX; ++e)
+          if (i0 + e < d.nx)
+#pragma unroll
+            for (int p = 0; p < NPOP; ++p)
+              o[(int64_t)p * d.plane + e] =
+                  C::enc(p < 9 ? f[e][p] : g[e][p - 9], pop_offset<C>(d, p));
+      }
+      if (tile_edge) {
+        const Dst<C> o{as_global(dst_raw), d.plane, d.pitch};
+        const float4 *in_next =
+            (tx == 0 && d.bc[0] == BC_INLET) ? d.inlet + (int64_t)((step + 1) % d.n_t) * d.nr
+                                              : d.inlet;
+#pragma unroll
+        for (int e = 0; e < NX; ++e) {
+          const int i = i0 + e;
+          if (i < d.nx && ((i == 0) | (i == d.nx - 1) | (j == 0) | (j == d.nr - 1)))
+            ghost_epilogue<C>(d, o, i, j, f[e], g[e], in_next);
+        }
+      }
     }
     if (!ok) flags[d.slot] = 1;
+  }
+}
+
+// Ghost ring of buf[step & 1] from its interior and the inlet row of `step`,
+// by the pull-side edge rules: every ghost slot (ghost node, link p) whose
+// puller (ghost + e_p) is a fluid node gets the value that node pulls.  Run
+// after any change of the interior or of the inlet made outside the step.
+// One thread per ghost node: row -1 and row nr (nx + 2 each, corners
+// included), then columns -1 and nx (nr each).
+template <class C>
+__global__ void ghost_fill_kernel(const JetDesc *__restrict__ dp, int64_t step) {
+  const JetDesc &d = *dp;
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nx = d.nx, nr = d.nr;
+  int gi, gj;
+  if (q < nx + 2) { gi = q - 1; gj = -1; }
+  else if (q < 2 * (nx + 2)) { gi = q - (nx + 2) - 1; gj = nr; }
+  else if (q < 2 * (nx + 2) + nr) { gi = -1; gj = q - 2 * (nx + 2); }
+  else if (q < 2 * (nx + 2) + 2 * nr) { gi = nx; gj = q - 2 * (nx + 2) - nr; }
+  else return;
+  using T = typename C::T;
+  T *raw = static_cast<T *>(d.buf[step & 1]);
+  const Src<C> s{as_global(static_cast<const T *>(raw)), d.plane, d.pitch};
+  const Dst<C> o{as_global(raw), d.plane, d.pitch};
+  const float4 *inrow = d.inlet + (int64_t)(step % d.n_t) * d.nr;
+#pragma unroll
+  for (int p = 1; p < NPOP; ++p) {
+    const int pi = gi + pex(p), pj = gj + per(p);
+    if (pi >= 0 && pi < nx && pj >= 0 && pj < nr)
+      o.put(d, p, gi, gj, pull_edge<C>(d, s, p, pi, pj, inrow));
   }
 }
 
@@ -83,7 +220,7 @@ __global__ void init_kernel(const JetDesc *__restrict__ dp, int64_t step,
   const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
   if (i >= d.nx) return;
   const float4 q = state ? state[(int64_t)j * d.nx + i] : u0;
-  typename C::T *o = static_cast<typename C::T *>(d.buf[step & 1]) + (int64_t)j * d.pitch + i;
+  typename C::T *o = static_cast<typename C::T *>(d.buf[step & 1]) + node_index(d.pitch, i, j);
 #pragma unroll
   for (int p = 0; p < NPOP; ++p)
     o[(int64_t)p * d.plane] = C::enc(eq_plane(p, q.x, q.y, q.z, q.w), pop_offset<C>(d, p));
@@ -97,10 +234,9 @@ __global__ void moments_kernel(const JetDesc *__restrict__ dp, int64_t step,
   const JetDesc &d = *dp;
   const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
   if (i >= d.nx) return;
-  Src<C> s{static_cast<const typename C::T *>(d.buf[step & 1]), d.plane, d.pitch};
-  const float4 *inrow = d.inlet + (int64_t)(step % d.n_t) * d.nr;
+  Src<C> s{as_global(static_cast<const typename C::T *>(d.buf[step & 1])), d.plane, d.pitch};
   float f[9], g[4];
-  pull_node<C>(d, s, i, j, inrow, f, g);
+  pull_node<C>(d, s, i, j, f, g);
   const float rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
   const float mx = (f[1] + f[5] + f[8]) - (f[3] + f[6] + f[7]);
   const float mr = (f[2] + f[5] + f[6]) - (f[4] + f[7] + f[8]);
@@ -117,10 +253,9 @@ __global__ void profiles_kernel(const JetDesc *__restrict__ dp, int64_t step,
   if (t >= d.nx + d.nr) return;
   const int i = t < d.nx ? t : d.nx - 1;
   const int j = t < d.nx ? 0 : t - d.nx;
-  Src<C> s{static_cast<const typename C::T *>(d.buf[step & 1]), d.plane, d.pitch};
-  const float4 *inrow = d.inlet + (int64_t)(step % d.n_t) * d.nr;
+  Src<C> s{as_global(static_cast<const typename C::T *>(d.buf[step & 1])), d.plane, d.pitch};
   float f[9], g[4];
-  pull_node<C>(d, s, i, j, inrow, f, g);
+  pull_node<C>(d, s, i, j, f, g);
   const float rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
   const float mx = (f[1] + f[5] + f[8]) - (f[3] + f[6] + f[7]);
   out[t] = make_float2(mx / rho, (g[0] + g[1]) + (g[2] + g[3]));
@@ -136,15 +271,14 @@ template <class C>
 __global__ __launch_bounds__(RED_THREADS) void conservation_kernel(
     const JetDesc *__restrict__ dp, int64_t step, RedPartial *__restrict__ partial) {
   const JetDesc &d = *dp;
-  Src<C> s{static_cast<const typename C::T *>(d.buf[step & 1]), d.plane, d.pitch};
-  const float4 *inrow = d.inlet + (int64_t)(step % d.n_t) * d.nr;
+  Src<C> s{as_global(static_cast<const typename C::T *>(d.buf[step & 1])), d.plane, d.pitch};
   const int64_t nodes = (int64_t)d.nx * d.nr;
   double m = 0.0, e = 0.0, bad = 0.0;
   for (int64_t n = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; n < nodes;
        n += (int64_t)gridDim.x * RED_THREADS) {
     const int j = (int)(n / d.nx), i = (int)(n - (int64_t)j * d.nx);
     float f[9], g[4];
-    pull_node<C>(d, s, i, j, inrow, f, g);
+    pull_node<C>(d, s, i, j, f, g);
     const float rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
     const float T = (g[0] + g[1]) + (g[2] + g[3]);
     const double r = (double)d.r0 + (double)j + 0.5;
@@ -201,7 +335,7 @@ __global__ void decode_kernel(const JetDesc *__restrict__ dp, int64_t step,
   if (i >= d.nx) return;
   const typename C::T *b = static_cast<const typename C::T *>(d.buf[step & 1]);
   out[((int64_t)p * d.nr + j) * d.nx + i] =
-      C::dec(b[(int64_t)p * d.plane + (int64_t)j * d.pitch + i], pop_offset<C>(d, p));
+      C::dec(b[(int64_t)p * d.plane + node_index(d.pitch, i, j)], pop_offset<C>(d, p));
 }
 
 template <class C>
@@ -211,7 +345,7 @@ __global__ void encode_kernel(const JetDesc *__restrict__ dp, int64_t step,
   const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y, p = blockIdx.z;
   if (i >= d.nx) return;
   typename C::T *b = static_cast<typename C::T *>(d.buf[step & 1]);
-  b[(int64_t)p * d.plane + (int64_t)j * d.pitch + i] =
+  b[(int64_t)p * d.plane + node_index(d.pitch, i, j)] =
       C::enc(in[((int64_t)p * d.nr + j) * d.nx + i], pop_offset<C>(d, p));
 }
 

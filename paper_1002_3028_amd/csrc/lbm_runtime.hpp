@@ -20,15 +20,13 @@ namespace lbmx {
   } while (0)
 
 constexpr int64_t NO_TARGET = INT64_MAX / 4;
-constexpr int32_t ROW_ALIGN = 64;  // elements; keeps every row 128 B+ aligned
 
 inline int storage_bytes(int prec) { return prec == LBM_PREC_FP32 ? 4 : 2; }
-inline int32_t pitch_of(int32_t nx) { return (nx + ROW_ALIGN - 1) / ROW_ALIGN * ROW_ALIGN; }
 inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
-// Bytes of one population buffer (13 planes).
+// Bytes of one population buffer (13 planes with their ghost rings).
 inline size_t buffer_bytes(const lbm_config *c, int prec) {
-  return align256((size_t)NPOP * (size_t)pitch_of(c->nx) * (size_t)c->nr * storage_bytes(prec));
+  return align256((size_t)NPOP * (size_t)layout_plane(c->nx, c->nr) * storage_bytes(prec));
 }
 
 int validate_config(const lbm_config *c, bool check_precision);
@@ -45,7 +43,7 @@ int make_inlet(const lbm_config *c, int32_t n_t, const double *ux, const double 
 
 // ---- kernel tables ---------------------------------------------------------
 struct TileShape {
-  int bx, by, ny;
+  int bx, by, ny, nx, waves;
   const void *fn[3];  // FP32, FP16-dev, BF16-dev
 };
 const TileShape *tile_shapes(int *count);
@@ -59,6 +57,8 @@ int launch_advance(hipStream_t st, JetDesc *jets, const BatchHdr *hdr, int32_t n
                    int32_t delta);
 int launch_init(int prec, hipStream_t st, const JetDesc *d, const lbm_config *c, int64_t step,
                 const float4 *state, float4 u0);
+int launch_ghost_fill(int prec, hipStream_t st, const JetDesc *d, const lbm_config *c,
+                      int64_t step);
 int launch_moments(int prec, hipStream_t st, const JetDesc *d, const lbm_config *c,
                    int64_t step, float4 *out);
 int launch_profiles(int prec, hipStream_t st, const JetDesc *d, const lbm_config *c,

@@ -92,7 +92,7 @@ _SIGS = {
     "lbm_batch_set_launch": ([_vp, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
     "lbm_batch_destroy": ([_vp], None),
     "lbm_tile_shape_count": ([], ctypes.c_int),
-    "lbm_tile_shape": ([ctypes.c_int32] + [ctypes.POINTER(ctypes.c_int32)] * 3, ctypes.c_int),
+    "lbm_tile_shape": ([ctypes.c_int32] + [ctypes.POINTER(ctypes.c_int32)] * 4, ctypes.c_int),
     "lbm_set_tile_shape": ([_vp, ctypes.c_int32], ctypes.c_int),
 }
 
@@ -190,10 +190,9 @@ def tile_shapes():
     lib = load()
     out = []
     for q in range(lib.lbm_tile_shape_count()):
-        bx, by, ny = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-        _check(lib.lbm_tile_shape(q, ctypes.byref(bx), ctypes.byref(by), ctypes.byref(ny)),
-               "lbm_tile_shape")
-        out.append((bx.value, by.value, ny.value))
+        v = [ctypes.c_int32() for _ in range(4)]
+        _check(lib.lbm_tile_shape(q, *[ctypes.byref(x) for x in v]), "lbm_tile_shape")
+        out.append(tuple(x.value for x in v))
     return out
 
 

@@ -39,8 +39,8 @@ def test_tile_shapes_listed(lib):
     from paper_1002_3028_amd import lbm
     shapes = lbm.tile_shapes()
     assert len(shapes) >= 4
-    for bx, by, ny in shapes:
-        assert bx % 64 == 0 and bx * by <= 1024 and ny >= 1
+    for bx, by, ny, nx in shapes:
+        assert bx % 64 == 0 and bx * by <= 1024 and ny >= 1 and nx in (1, 2, 4, 8)
 
 
 def _params(**kw):
@@ -75,11 +75,14 @@ def test_precision_validated(lib):
 
 
 def test_bytes_required(lib):
+    """Two buffers of 13 planes; a plane holds nr + 2 rows (ghost rows) of a
+    pitch that leaves 64 leading elements, the ghost column and vector slack."""
     from paper_1002_3028_amd import lbm
     p = _params(nx=100, nr=30)
-    pitch = 128  # rows padded to 64 elements
-    assert lbm.bytes_required(p, "fp32") == 2 * ((13 * pitch * 30 * 4 + 255) // 256 * 256)
-    assert lbm.bytes_required(p, "fp16") == 2 * ((13 * pitch * 30 * 2 + 255) // 256 * 256)
+    pitch = 192  # 64 + 100 + 1 + 8 rounded up to 64
+    rows = 32
+    assert lbm.bytes_required(p, "fp32") == 2 * ((13 * pitch * rows * 4 + 255) // 256 * 256)
+    assert lbm.bytes_required(p, "fp16") == 2 * ((13 * pitch * rows * 2 + 255) // 256 * 256)
 
 
 def test_strerror(lib):
