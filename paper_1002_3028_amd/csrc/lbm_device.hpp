@@ -92,7 +92,7 @@ struct alignas(16) JetDesc {
   int32_t bc[4];
   float r0, nu0, alpha0, c18;      // c18 = 18 (C_s Delta)^2
   float inv_prt, G, t_lo, t_scale; // t_scale = (table_n - 1) / (t_hi - t_lo)
-  float rho_ref, g4_ref, pad0, pad1;
+  float rho_ref, g4_ref, one, pad1;  // one = 1.0f, kept opaque to the compiler
   float wallT[4];                  // NaN: adiabatic
   float eq[4][4];                  // EQ side: rho, ux, ur, T
 };
@@ -117,23 +117,30 @@ struct RedPartial {
 // store the deviation from a reference (w_k rho_ref for f, g_ref/4 for g)
 // rounded to nearest even, and decode to FP32.
 // ---------------------------------------------------------------------------
+// `one` is 1.0f from the descriptor: with it the FP16 codec maps onto the
+// mixed-precision FMA (decode: h * 1 + offset in one instruction; encode: the
+// exact f - offset rounded once to binary16).
 struct CodecF32 {
   using T = float;
   static constexpr bool dev = false;
-  __device__ static __forceinline__ float dec(T v, float) { return v; }
-  __device__ static __forceinline__ T enc(float v, float) { return v; }
+  __device__ static __forceinline__ float dec(T v, float, float) { return v; }
+  __device__ static __forceinline__ T enc(float v, float, float) { return v; }
 };
 struct CodecF16 {
   using T = _Float16;
   static constexpr bool dev = true;
-  __device__ static __forceinline__ float dec(T v, float off) { return (float)v + off; }
-  __device__ static __forceinline__ T enc(float v, float off) { return (T)(v - off); }
+  __device__ static __forceinline__ float dec(T v, float off, float one) {
+    return __builtin_fmaf((float)v, one, off);
+  }
+  __device__ static __forceinline__ T enc(float v, float off, float one) {
+    return (T)__builtin_fmaf(v, one, -off);
+  }
 };
 struct CodecBF16 {
   using T = __bf16;
   static constexpr bool dev = true;
-  __device__ static __forceinline__ float dec(T v, float off) { return (float)v + off; }
-  __device__ static __forceinline__ T enc(float v, float off) { return (T)(v - off); }
+  __device__ static __forceinline__ float dec(T v, float off, float) { return (float)v + off; }
+  __device__ static __forceinline__ T enc(float v, float off, float) { return (T)(v - off); }
 };
 
 template <class C>
@@ -146,13 +153,22 @@ __device__ __forceinline__ float pop_offset(const JetDesc &d, int p) {
 // Equilibria (moments fixed by eq. 2): second-order D2Q9, c_s^2 = 1/3;
 // first-order D2Q4, c_s^2 = 1/2.
 // ---------------------------------------------------------------------------
+// e . v for lattice components in {-1, 0, 1}: operands are selected, not
+// multiplied, so that zero components add no instruction once k is known.
+__device__ __forceinline__ float proj(int ex, int er, float vx, float vr) {
+  if (ex == 0 && er == 0) return 0.0f;
+  if (ex == 0) return er > 0 ? vr : -vr;
+  if (er == 0) return ex > 0 ? vx : -vx;
+  return (ex > 0 ? vx : -vx) + (er > 0 ? vr : -vr);
+}
+
 __device__ __forceinline__ float feq_link(int k, float rho, float ux, float ur) {
-  const float eu = (float)ex9(k) * ux + (float)er9(k) * ur;
+  const float eu = proj(ex9(k), er9(k), ux, ur);
   const float uu = ux * ux + ur * ur;
   return w9(k) * rho * (1.0f + 3.0f * eu + 4.5f * eu * eu - 1.5f * uu);
 }
 __device__ __forceinline__ float geq_link(int k, float T, float ux, float ur) {
-  const float eu = (float)ex4(k) * ux + (float)er4(k) * ur;
+  const float eu = proj(ex4(k), er4(k), ux, ur);
   return 0.25f * T * (1.0f + 2.0f * eu);
 }
 // equilibrium of storage plane p
@@ -187,7 +203,8 @@ __device__ __forceinline__ bool collide(const JetDesc &d, float rinv, float r2,
     const float fn = f[k] - feq_link(k, rho, ux, ur);
     if (ex9(k) != 0) qxx += fn;
     if (er9(k) != 0) qrr += fn;
-    if (ex9(k) * er9(k) != 0) qxr += (float)(ex9(k) * er9(k)) * fn;
+    if (ex9(k) * er9(k) > 0) qxr += fn;
+    if (ex9(k) * er9(k) < 0) qxr -= fn;
   }
   // sum_k e_kr g_k^neq (the links +r and -r)
   const float jr = (g[1] - geq_link(1, T, ux, ur)) - (g[3] - geq_link(3, T, ux, ur));
@@ -225,8 +242,8 @@ __device__ __forceinline__ bool collide(const JetDesc &d, float rinv, float r2,
   const float fx6 = Fx * (1.0f / 6.0f), fr6 = Fr * (1.0f / 6.0f);
 #pragma unroll
   for (int k = 0; k < 9; ++k)
-    f[k] = f[k] - (f[k] - feq_link(k, rho, ux, ur)) * itau + w9(k) * theta +
-           (float)ex9(k) * fx6 + (float)er9(k) * fr6;
+    f[k] = f[k] - (f[k] - feq_link(k, rho, ux, ur)) * itau +
+           (w9(k) * theta + proj(ex9(k), er9(k), fx6, fr6));
   const float s4 = 0.25f * S;
 #pragma unroll
   for (int k = 0; k < 4; ++k) g[k] = g[k] - (g[k] - geq_link(k, T, ux, ur)) * itau_a + s4;
@@ -243,7 +260,7 @@ struct Src {
   int64_t plane;
   int32_t pitch;
   __device__ __forceinline__ float load(const JetDesc &d, int p, int i, int j) const {
-    return C::dec(base[(int64_t)p * plane + node_index(pitch, i, j)], pop_offset<C>(d, p));
+    return C::dec(base[(int64_t)p * plane + node_index(pitch, i, j)], pop_offset<C>(d, p), d.one);
   }
 };
 
@@ -253,7 +270,7 @@ struct Dst {
   int64_t plane;
   int32_t pitch;
   __device__ __forceinline__ void put(const JetDesc &d, int p, int i, int j, float v) const {
-    base[(int64_t)p * plane + node_index(pitch, i, j)] = C::enc(v, pop_offset<C>(d, p));
+    base[(int64_t)p * plane + node_index(pitch, i, j)] = C::enc(v, pop_offset<C>(d, p), d.one);
   }
 };
 

@@ -102,7 +102,8 @@ void fill_desc(JetDesc &d, const lbm_config *c) {
   d.t_scale = c->table_n == 0 ? 0.f : (float)((c->table_n - 1) / (c->t_hi - c->t_lo));
   d.rho_ref = (float)c->rho_ref;
   d.g4_ref = (float)(0.25 * c->g_ref);
-  d.pad0 = d.pad1 = 0.f;
+  d.one = 1.0f;
+  d.pad1 = 0.f;
 }
 
 int make_inlet(const lbm_config *c, int32_t n_t, const double *ux, const double *ur,
@@ -123,17 +124,18 @@ int make_inlet(const lbm_config *c, int32_t n_t, const double *ux, const double 
 }
 
 // ---- tile shapes -------------------------------------------------------------
-#define LBM_SHAPE(BX, BY, NY, NX, W)                                             \
-  {BX, BY, NY, NX, W,                                                            \
-   {(const void *)&step_kernel<CodecF32, BX, BY, NY, NX, W>,                     \
-    (const void *)&step_kernel<CodecF16, BX, BY, NY, NX, W>,                     \
-    (const void *)&step_kernel<CodecBF16, BX, BY, NY, NX, W>}}
+#define LBM_SHAPE(BX, BY, NY, NX, W, CP)                                         \
+  {BX, BY, NY, NX, W, CP,                                                        \
+   {(const void *)&step_kernel<CodecF32, BX, BY, NY, NX, W, CP>,                 \
+    (const void *)&step_kernel<CodecF16, BX, BY, NY, NX, W, CP>,                 \
+    (const void *)&step_kernel<CodecBF16, BX, BY, NY, NX, W, CP>}}
 
 static const TileShape kShapes[] = {
-    LBM_SHAPE(64, 4, 1, 1, 1),  LBM_SHAPE(128, 2, 1, 1, 1), LBM_SHAPE(256, 1, 1, 1, 1),
-    LBM_SHAPE(64, 8, 1, 1, 1),  LBM_SHAPE(64, 4, 2, 1, 1),  LBM_SHAPE(64, 4, 1, 2, 1),
-    LBM_SHAPE(128, 2, 1, 2, 1), LBM_SHAPE(256, 1, 1, 2, 1), LBM_SHAPE(64, 4, 1, 4, 1),
-    LBM_SHAPE(64, 2, 1, 4, 1),  LBM_SHAPE(64, 1, 1, 4, 1),  LBM_SHAPE(128, 1, 1, 2, 1),
+    LBM_SHAPE(64, 4, 1, 1, 1, 0),  LBM_SHAPE(128, 2, 1, 1, 1, 0), LBM_SHAPE(256, 1, 1, 1, 1, 0),
+    LBM_SHAPE(64, 8, 1, 1, 1, 0),  LBM_SHAPE(64, 4, 2, 1, 1, 0),  LBM_SHAPE(64, 4, 1, 2, 1, 0),
+    LBM_SHAPE(128, 2, 1, 2, 1, 0), LBM_SHAPE(64, 4, 1, 1, 1, 1),  LBM_SHAPE(64, 4, 1, 1, 1, 2),
+    LBM_SHAPE(64, 4, 1, 1, 1, 3),  LBM_SHAPE(64, 4, 2, 1, 1, 1),  LBM_SHAPE(64, 4, 2, 1, 1, 3),
+    LBM_SHAPE(128, 2, 1, 1, 1, 1), LBM_SHAPE(64, 8, 2, 1, 1, 0),
 };
 #undef LBM_SHAPE
 

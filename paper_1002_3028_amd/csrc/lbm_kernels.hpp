@@ -15,22 +15,24 @@ template <> struct Raw<4> { typedef uint32_t type; };
 template <> struct Raw<8> { typedef uint32_t type __attribute__((ext_vector_type(2))); };
 template <> struct Raw<16> { typedef uint32_t type __attribute__((ext_vector_type(4))); };
 
-template <int B>
+// AUX is the cache-policy field of the instruction (2: non-temporal).
+template <int B, int AUX>
 __device__ __forceinline__ typename Raw<B>::type buf_load(__amdgpu_buffer_rsrc_t r, uint32_t voff,
                                                           uint32_t soff) {
-  if constexpr (B == 2) return __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
-  else if constexpr (B == 4) return __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0);
-  else if constexpr (B == 8) return __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0);
-  else return __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0);
+  if constexpr (B == 2) return __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, AUX);
+  else if constexpr (B == 4) return __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, AUX);
+  else if constexpr (B == 8) return __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, AUX);
+  else return __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, AUX);
 }
-template <int B>
+template <int B, int AUX>
 __device__ __forceinline__ void buf_store(typename Raw<B>::type v, __amdgpu_buffer_rsrc_t r,
                                           uint32_t voff, uint32_t soff) {
-  if constexpr (B == 2) __builtin_amdgcn_raw_buffer_store_b16(v, r, voff, soff, 0);
-  else if constexpr (B == 4) __builtin_amdgcn_raw_buffer_store_b32(v, r, voff, soff, 0);
-  else if constexpr (B == 8) __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, soff, 0);
-  else __builtin_amdgcn_raw_buffer_store_b128(v, r, voff, soff, 0);
+  if constexpr (B == 2) __builtin_amdgcn_raw_buffer_store_b16(v, r, voff, soff, AUX);
+  else if constexpr (B == 4) __builtin_amdgcn_raw_buffer_store_b32(v, r, voff, soff, AUX);
+  else if constexpr (B == 8) __builtin_amdgcn_raw_buffer_store_b64(v, r, voff, soff, AUX);
+  else __builtin_amdgcn_raw_buffer_store_b128(v, r, voff, soff, AUX);
 }
+constexpr int CACHE_NT = 2;
 
 // NX elements of storage type T packed in one raw word
 template <class T, int NX>
@@ -59,11 +61,12 @@ __device__ __forceinline__ T elem(const typename Pack<T, NX>::vec &v, int e) {
 // Workgroups walk the tile list with a grid stride; within each round the
 // tiles handed to one XCD (workgroup id mod 8) are contiguous, so the
 // columns that x-shifted pulls share with the neighbouring tile stay in one
-// L2.  W is the occupancy target (waves per SIMD) for register allocation.
+// L2.  W is the occupancy target (waves per SIMD) for register allocation;
+// CP selects non-temporal stores (bit 0) and loads (bit 1).
 // The jet's state after s steps lives in buf[s & 1]; the step taken here is
 // step0 + koff, skipped once the jet reaches its target.
 // ---------------------------------------------------------------------------
-template <class C, int BX, int BY, int NY, int NX, int W>
+template <class C, int BX, int BY, int NY, int NX, int W, int CP>
 __global__ __launch_bounds__(BX *BY) __attribute__((amdgpu_waves_per_eu(W, 8))) void step_kernel(
     const JetDesc *__restrict__ jets, const int32_t *__restrict__ tile_start,
     const BatchHdr *__restrict__ hdr, int32_t koff, int32_t *__restrict__ flags) {
@@ -115,11 +118,11 @@ __global__ __launch_bounds__(BX *BY) __attribute__((amdgpu_waves_per_eu(W, 8))) 
         // because plane p >= 1 starts at least a plane after the buffer
         const uint32_t soff = (uint32_t)p * plane_b - (uint32_t)(per(p) * (int)pitch_b) -
                               (uint32_t)(pex(p) * ES);
-        const VT v = __builtin_bit_cast(VT, buf_load<VB>(rs, voff, soff));
+        const VT v = __builtin_bit_cast(VT, buf_load<VB, (CP & 2) ? CACHE_NT : 0>(rs, voff, soff));
         const float off = pop_offset<C>(d, p);
 #pragma unroll
         for (int e = 0; e < NX; ++e) {
-          const float x = C::dec(elem<T, NX>(v, e), off);
+          const float x = C::dec(elem<T, NX>(v, e), off, d.one);
           if (p < 9) f[e][p] = x; else g[e][p - 9] = x;
         }
       }
@@ -137,11 +140,11 @@ __global__ __launch_bounds__(BX *BY) __attribute__((amdgpu_waves_per_eu(W, 8))) 
           VT v;
 #pragma unroll
           for (int e = 0; e < NX; ++e) {
-            const T x = C::enc(p < 9 ? f[e][p] : g[e][p - 9], off);
+            const T x = C::enc(p < 9 ? f[e][p] : g[e][p - 9], off, d.one);
             if constexpr (NX == 1) v = x; else v[e] = x;
           }
-          buf_store<VB>(__builtin_bit_cast(typename Raw<VB>::type, v), rd, voff,
-                        (uint32_t)p * plane_b);
+          buf_store<VB, (CP & 1) ? CACHE_NT : 0>(__builtin_bit_cast(typename Raw<VB>::type, v), rd,
+                                                 voff, (uint32_t)p * plane_b);
         }
       } else {
         const gptr<T> o = as_global(dst_raw) + node_index(d.pitch, i0, j);
@@ -151,7 +154,7 @@ __global__ __launch_bounds__(BX *BY) __attribute__((amdgpu_waves_per_eu(W, 8))) 
 #pragma unroll
             for (int p = 0; p < NPOP; ++p)
               o[(int64_t)p * d.plane + e] =
-                  C::enc(p < 9 ? f[e][p] : g[e][p - 9], pop_offset<C>(d, p));
+                  C::enc(p < 9 ? f[e][p] : g[e][p - 9], pop_offset<C>(d, p), d.one);
       }
       if (tile_edge) {
         const Dst<C> o{as_global(dst_raw), d.plane, d.pitch};
@@ -223,7 +226,7 @@ __global__ void init_kernel(const JetDesc *__restrict__ dp, int64_t step,
   typename C::T *o = static_cast<typename C::T *>(d.buf[step & 1]) + node_index(d.pitch, i, j);
 #pragma unroll
   for (int p = 0; p < NPOP; ++p)
-    o[(int64_t)p * d.plane] = C::enc(eq_plane(p, q.x, q.y, q.z, q.w), pop_offset<C>(d, p));
+    o[(int64_t)p * d.plane] = C::enc(eq_plane(p, q.x, q.y, q.z, q.w), pop_offset<C>(d, p), d.one);
 }
 
 // Pre-collision moments (eq. 2) of buf[step & 1] at step `step`:
@@ -335,7 +338,7 @@ __global__ void decode_kernel(const JetDesc *__restrict__ dp, int64_t step,
   if (i >= d.nx) return;
   const typename C::T *b = static_cast<const typename C::T *>(d.buf[step & 1]);
   out[((int64_t)p * d.nr + j) * d.nx + i] =
-      C::dec(b[(int64_t)p * d.plane + node_index(d.pitch, i, j)], pop_offset<C>(d, p));
+      C::dec(b[(int64_t)p * d.plane + node_index(d.pitch, i, j)], pop_offset<C>(d, p), d.one);
 }
 
 template <class C>
@@ -346,7 +349,7 @@ __global__ void encode_kernel(const JetDesc *__restrict__ dp, int64_t step,
   if (i >= d.nx) return;
   typename C::T *b = static_cast<typename C::T *>(d.buf[step & 1]);
   b[(int64_t)p * d.plane + node_index(d.pitch, i, j)] =
-      C::enc(in[((int64_t)p * d.nr + j) * d.nx + i], pop_offset<C>(d, p));
+      C::enc(in[((int64_t)p * d.nr + j) * d.nx + i], pop_offset<C>(d, p), d.one);
 }
 
 // Plain streaming copy, 16 B per lane per iteration.

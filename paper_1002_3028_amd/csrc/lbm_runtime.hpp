@@ -43,7 +43,7 @@ int make_inlet(const lbm_config *c, int32_t n_t, const double *ux, const double 
 
 // ---- kernel tables ---------------------------------------------------------
 struct TileShape {
-  int bx, by, ny, nx, waves;
+  int bx, by, ny, nx, waves, cache;
   const void *fn[3];  // FP32, FP16-dev, BF16-dev
 };
 const TileShape *tile_shapes(int *count);
