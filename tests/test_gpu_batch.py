@@ -1,0 +1,166 @@
+"""Many jets in one persistent launch: each jet's result is bitwise the same
+alone and in the mix (same kernel, no cross-jet arithmetic), jets finish at
+their own step counts, admission respects the HBM budget, and jets admitted
+while others run (continuous batching) are unaffected by their neighbours.
+"""
+import numpy as np
+import pytest
+
+from gpu_common import host_threads, noisy_inlet, rel_err, require_gpu, speed, tiny_params
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def _jets():
+    from paper_1002_3028_amd import inputs
+    out = []
+    for q, (nx, nr) in enumerate([(200, 45), (64, 16), (333, 70), (128, 32)]):
+        p = tiny_params(nx, nr, "jet", q % 2)
+        p["cs"] = 0.1 + 0.03 * q
+        out.append((p, noisy_inlet(nr, 3 + q, q), 60 + 17 * q))
+    p, inlet, _ = inputs.workload_small()
+    out.append((p, inlet, 90))
+    return out
+
+
+def _moments_after(batch, slots):
+    return {s: batch.moments(s) for s in slots}
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+def test_alone_equals_in_mix(precision):
+    from paper_1002_3028_amd import lbm
+    jets = _jets()
+    with lbm.Batch(1 << 30, 16, precision) as mix:
+        slots = [mix.admit(p, inlet, steps) for p, inlet, steps in jets]
+        for _ in range(12):
+            mix.run(10)
+        assert [mix.poll(s) for s in slots] == [steps for _, _, steps in jets]
+        mixed = _moments_after(mix, slots)
+    for q, (p, inlet, steps) in enumerate(jets):
+        with lbm.Batch(1 << 28, 2, precision) as alone:
+            s = alone.admit(p, inlet, steps)
+            alone.run(steps + 5)
+            assert alone.poll(s) == steps
+            m = alone.moments(s)
+        for key in m:
+            assert np.array_equal(m[key], mixed[slots[q]][key]), (q, key)
+
+
+def test_batch_matches_single_solver_and_oracle():
+    """A batched jet equals the single-jet solver bitwise and the oracle to
+    the FP32 tolerance."""
+    import oracle
+    from paper_1002_3028_amd import lbm
+    p, inlet, steps = _jets()[2]
+    with lbm.Batch(1 << 28, 4, "fp32") as b:
+        s = b.admit(p, inlet, steps)
+        b.run(steps)
+        mb = b.moments(s)
+        pb = b.profiles(s)
+    with lbm.Solver(p, "fp32") as g:
+        g.set_inlet(*inlet)
+        g.step(steps)
+        mg = g.moments()
+    for key in mg:
+        assert np.array_equal(mb[key], mg[key]), key
+    with oracle.RefSolver(p, threads=host_threads()) as r:
+        r.set_inlet(*inlet)
+        r.step(steps)
+        mr = r.moments()
+    assert rel_err(speed(mb), speed(mr)) < 1e-4 and rel_err(mb["T"], mr["T"]) < 1e-4
+    np.testing.assert_array_equal(pb["ux_axis"], mb["ux"][0])
+    np.testing.assert_array_equal(pb["T_exit"], mb["T"][:, -1])
+
+
+def test_continuous_admission_and_retire():
+    """Jets admitted while others are mid-run and slots reused after
+    retirement give the same result as each jet alone."""
+    from paper_1002_3028_amd import lbm
+    jets = _jets()
+    refs = []
+    for p, inlet, steps in jets:
+        with lbm.Batch(1 << 28, 2, "fp32") as alone:
+            s = alone.admit(p, inlet, steps)
+            alone.run(steps)
+            refs.append(alone.moments(s))
+    with lbm.Batch(1 << 30, 3, "fp32") as b:
+        pending = list(range(len(jets)))
+        live = {}
+        done = {}
+        rounds = 0
+        while (pending or live) and rounds < 200:
+            rounds += 1
+            while pending:
+                q = pending[0]
+                p, inlet, steps = jets[q]
+                rc, slot = b.try_admit(p, inlet, steps)
+                if rc == lbm.ENOMEM:
+                    break
+                assert rc == lbm.OK
+                live[slot] = q
+                pending.pop(0)
+            b.run(7)
+            for slot, q in list(live.items()):
+                if b.poll(slot) == jets[q][2]:
+                    done[q] = b.moments(slot)
+                    b.retire(slot)
+                    del live[slot]
+        assert len(done) == len(jets)
+    for q in range(len(jets)):
+        for key in refs[q]:
+            assert np.array_equal(done[q][key], refs[q][key]), (q, key)
+
+
+def test_budget_admission():
+    from paper_1002_3028_amd import lbm
+    p = tiny_params(256, 64, "jet", 1)
+    with lbm.Batch(1 << 24, 8, "fp32") as b:
+        need = b.jet_bytes(p)
+        n_fit = (1 << 24) // need
+        slots = []
+        for _ in range(n_fit):
+            rc, s = b.try_admit(p, None, 10)
+            assert rc == lbm.OK
+            slots.append(s)
+        rc, s = b.try_admit(p, None, 10)
+        assert rc == lbm.ENOMEM and s == -1
+        n_act, used = b.active()
+        assert n_act == n_fit and used == n_fit * need
+        b.retire(slots[0])
+        rc, s = b.try_admit(p, None, 10)
+        assert rc == lbm.OK
+    with lbm.Batch(1 << 30, 2, "fp32") as b:
+        b.admit(p, None, 5)
+        b.admit(p, None, 5)
+        rc, _ = b.try_admit(p, None, 5)
+        assert rc == lbm.ENOMEM  # slot table full
+
+
+def test_unstable_jet_fails_alone():
+    """A runaway jet is flagged for its own slot only; its batch mates'
+    results are unchanged."""
+    from paper_1002_3028_amd import inputs, lbm
+    good = _jets()[1]
+    bad_p = tiny_params(64, 16, "jet", 0)
+    bad_inlet = inputs.inlet_rows(16, 8.0, 0.9, 5.0)
+    with lbm.Batch(1 << 28, 2, "fp32") as alone:
+        s = alone.admit(*good)
+        alone.run(good[2])
+        ref = alone.moments(s)
+    with lbm.Batch(1 << 28, 4, "fp32") as b:
+        sg = b.admit(*good)
+        sb = b.admit(bad_p, bad_inlet, 400)
+        for _ in range(40):
+            b.run(10)
+        m = b.moments(sg)
+        with pytest.raises(lbm.LbmError) as e:
+            b.moments(sb)
+        assert e.value.code == lbm.EUNSTABLE
+    for key in ref:
+        assert np.array_equal(m[key], ref[key])
