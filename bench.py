@@ -83,6 +83,64 @@ def time_jet(params, inlet, precision, steps, warmup, graph_steps=50, check_ever
     return t1 - t0, ev_ms / steps, mass
 
 
+def bench_batch(n_jets=64, steps=500, precision="fp32"):
+    """64 jets of uneven sizes (seed 2) advanced together in one persistent
+    launch per step, against the same jets run one after another through the
+    single-jet path (same kernel).  Aggregate GLUPS of both."""
+    import torch
+    from paper_1002_3028_amd import inputs, lbm
+
+    jets = inputs.batch_jets(n_jets, seed=2, steps=steps)
+    nodes = sum(p["nx"] * p["nr"] for p, _, _ in jets)
+    budget = sum(lbm.bytes_required(p, precision) for p, _, _ in jets) + (64 << 20)
+    with lbm.Batch(budget, n_jets, precision) as b:
+        for p, inlet, _ in jets:
+            b.admit(p, inlet, steps + 100)
+        b.run(50)
+        b.sync()
+        t0 = time.perf_counter()
+        for _ in range(steps // 50):
+            b.run(50)
+        b.sync()
+        t_batch = time.perf_counter() - t0
+    solvers = []
+    for p, inlet, _ in jets:
+        s = lbm.Solver(p, precision, graph_steps=50)
+        s.set_inlet(*inlet)
+        s.step(50)
+        solvers.append(s)
+    torch.cuda.synchronize()
+    for s in solvers:
+        s.sync()
+    t0 = time.perf_counter()
+    for s in solvers:
+        s.step(steps)
+        s.sync()
+    t_loop = time.perf_counter() - t0
+    for s in solvers:
+        s.close()
+    upd = nodes * (steps // 50) * 50
+    return {"jets": n_jets, "nodes": nodes, "steps": (steps // 50) * 50, "precision": precision,
+            "batched_glups": round(upd / t_batch / 1e9, 3),
+            "looped_single_glups": round(nodes * steps / t_loop / 1e9, 3)}
+
+
+def bench_serving(n_requests=200, precision="fp16"):
+    """Poisson trace (seed 3): capacity with every request admitted at once,
+    then p50/p99 latency at 0.7 x that rate."""
+    from paper_1002_3028_amd import inputs, serve
+
+    cap, _ = serve.serve(inputs.arrival_trace(n_requests, 3, rate=1.0), precision,
+                         16 << 30, 256, 50, realtime=False)
+    rate = 0.7 * cap["requests_per_s"]
+    run, _ = serve.serve(inputs.arrival_trace(n_requests, 3, rate=rate), precision,
+                         16 << 30, 256, 50, realtime=True)
+    return {"requests": n_requests, "precision": precision,
+            "capacity_req_per_s": cap["requests_per_s"], "capacity_glups": cap["glups"],
+            "rate_req_per_s": round(rate, 3), "p50_s": run["p50_s"], "p99_s": run["p99_s"],
+            "glups_at_rate": run["glups"]}
+
+
 def cpu_baseline(params, inlet, budget_s=12.0):
     import oracle
 
@@ -170,6 +228,9 @@ def main():
             extra[f"{prec}_4096x1024"] = {
                 "glups": round(g, 3),
                 "hbm_frac": round(BYTES_PER_NODE[prec] * nodes_l / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        extra["batch_64_jets"] = bench_batch()
+        extra["serving_fp16"] = bench_serving(precision="fp16")
+        extra["serving_fp32"] = bench_serving(precision="fp32")
         line["extra"] = extra
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(p, inlet)

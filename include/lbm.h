@@ -155,13 +155,15 @@ const char *lbm_strerror(int code);
  * the HBM traffic counters against a transfer of known size. */
 int lbm_probe_copy(void *dst, const void *src, size_t bytes, void *hip_stream);
 
-/* ---- many jets in one persistent launch ----------------------------------
+/* ---- many jets in persistent launches -------------------------------------
  * A batch owns up to max_slots resident jets whose population buffers are
  * carved out of budget_bytes of device memory.  lbm_batch_run advances every
- * active jet by up to k steps with one launch per step (grouped into HIP
- * graphs); a jet stops at its own target step count.  Each jet's result is
- * bitwise the same as that of the same jet run alone through the batch.
- * Precision is common to the batch. */
+ * active jet by up to k steps: the active jets are grouped into cohorts of
+ * at most cohort_bytes of buffers (default 200 MiB, so that a cohort stays in
+ * the Infinity Cache), and each cohort gets k steps of one persistent launch
+ * per step over all its jets (HIP graphs), cohort after cohort.  A jet stops
+ * at its own target step count.  Each jet's result is bitwise the same as
+ * that of the same jet run alone.  Precision is common to the batch. */
 typedef struct lbm_batch lbm_batch;
 int lbm_batch_create(size_t budget_bytes, int32_t max_slots, int32_t precision,
                      void *hip_stream, lbm_batch **out);
@@ -178,12 +180,16 @@ int lbm_batch_profiles(lbm_batch *b, int32_t slot, double *ux_axis, double *T_ax
 int lbm_batch_moments(lbm_batch *b, int32_t slot, double *rho, double *ux,
                       double *ur, double *T);
 int lbm_batch_retire(lbm_batch *b, int32_t slot);
+/* Wait for the batch's queued work; LBM_EDEVICE on an asynchronous error. */
+int lbm_batch_sync(lbm_batch *b);
 /* Bytes a jet of this configuration takes from the budget. */
 int lbm_batch_jet_bytes(const lbm_batch *b, const lbm_config *cfg, size_t *bytes);
 int lbm_batch_active(const lbm_batch *b, int32_t *n_active, size_t *bytes_used);
 /* Tile shape of the step kernel (index into the compiled shapes; -1 = auto)
  * and the number of persistent workgroups (0 = auto). */
 int lbm_batch_set_launch(lbm_batch *b, int32_t tile_shape, int32_t workgroups);
+/* Cohort size limit in bytes of population buffers (0: all jets together). */
+int lbm_batch_set_cohort_bytes(lbm_batch *b, size_t bytes);
 void lbm_batch_destroy(lbm_batch *b);
 
 /* Compiled tile shapes of the step kernel: count, and one shape: a workgroup

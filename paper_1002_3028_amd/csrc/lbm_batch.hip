@@ -1,9 +1,13 @@
-// lbm_batch.hip -- many resident jets advanced by one persistent launch per
-// step.  Population buffers are carved out of one device arena (the HBM
-// budget) by a first-fit allocator; every active jet has a descriptor, and
-// the step kernel walks a flat tile list covering all of them.  The launch
-// configuration (grid, kernel arguments) never changes with the set of
-// jets, so a captured graph of k steps is replayed as jets come and go.
+// lbm_batch.hip -- many resident jets advanced by persistent launches.
+// Population buffers are carved out of one device arena (the HBM budget) by
+// a first-fit allocator.  Active jets are grouped into cohorts whose buffers
+// together fit the Infinity Cache; a run of k steps advances cohort after
+// cohort, each with one launch per step over a flat tile list covering the
+// cohort's jets, so every cohort's working set stays cache-resident for its
+// k steps.  Each cohort has fixed device arrays (descriptors, tile prefix
+// sums, header) and the launch configuration never changes with the set of
+// jets, so the captured graph of k steps of a cohort is replayed as jets come
+// and go.
 #include <algorithm>
 #include <map>
 #include <tuple>
@@ -72,10 +76,13 @@ struct lbm_batch {
   void *arena_mem = nullptr;
   Arena arena;
   std::vector<Slot> slots;
-  JetDesc *d_jets = nullptr;     // compact list of active jets
+  JetDesc *d_jets = nullptr;     // per cohort: compact list of its jets
   JetDesc *d_slot_desc = nullptr;  // per slot, for the single-jet helper kernels
-  int32_t *d_tiles = nullptr;
-  BatchHdr *d_hdr = nullptr;
+  int32_t *d_tiles = nullptr;      // per cohort: tile prefix sums
+  BatchHdr *d_hdr = nullptr;       // per cohort: number of jets
+  int32_t max_cohorts = 0;
+  int32_t n_cohorts = 0;
+  size_t cohort_bytes = size_t(200) << 20;  // 0: one cohort
   int32_t *d_flags = nullptr;
   Scratch scratch;
   std::vector<int32_t> active;  // slots in the compact list, in order
@@ -83,7 +90,7 @@ struct lbm_batch {
   int shape = -1;       // -1: auto
   int32_t wg = 0;       // 0: auto
   int32_t grid = 0;
-  std::map<std::tuple<int, int, int>, hipGraphExec_t> graphs;  // (k, shape, grid)
+  std::map<std::tuple<int, int, int, int>, hipGraphExec_t> graphs;  // (k, shape, grid, cohort)
 };
 
 namespace {
@@ -95,30 +102,53 @@ void drop_graphs(lbm_batch *b) {
   b->graphs.clear();
 }
 
-// Rebuild and upload the compact jet list and tile prefix sums.
+// Rebuild and upload the cohorts: active jets in slot order, a new cohort
+// whenever the next jet's buffers would take the cohort past cohort_bytes.
 int rebuild(lbm_batch *b) {
   const int shape = pick_shape(b);
-  std::vector<JetDesc> jets;
-  std::vector<int32_t> start(1, 0);
+  const int32_t ms = (int32_t)b->slots.size();
+  std::vector<std::vector<JetDesc>> jets(1);
+  std::vector<std::vector<int32_t>> start(1, std::vector<int32_t>(1, 0));
+  std::vector<size_t> bytes(1, 0);
   b->active.clear();
-  for (int32_t s = 0; s < (int32_t)b->slots.size(); ++s) {
+  for (int32_t s = 0; s < ms; ++s) {
     Slot &sl = b->slots[s];
     if (!sl.used || sl.step >= sl.target) continue;
+    if (b->cohort_bytes && !jets.back().empty() &&
+        bytes.back() + sl.bytes > b->cohort_bytes && (int32_t)jets.size() < b->max_cohorts) {
+      jets.emplace_back();
+      start.emplace_back(1, 0);
+      bytes.push_back(0);
+    }
     int32_t tx;
     const int nt = tiles_of(&sl.cfg, shape, &tx);
     sl.desc.tiles_x = tx;
     sl.desc.step0 = sl.step;
-    jets.push_back(sl.desc);
-    start.push_back(start.back() + nt);
+    jets.back().push_back(sl.desc);
+    start.back().push_back(start.back().back() + nt);
+    bytes.back() += sl.bytes;
     b->active.push_back(s);
   }
-  const int32_t n = (int32_t)jets.size();
-  BatchHdr hdr{n, {0, 0, 0}};
   LBM_HIP(hipStreamSynchronize(b->stream));
-  if (n) LBM_HIP(hipMemcpy(b->d_jets, jets.data(), n * sizeof(JetDesc), hipMemcpyHostToDevice));
-  LBM_HIP(hipMemcpy(b->d_tiles, start.data(), start.size() * sizeof(int32_t),
-                    hipMemcpyHostToDevice));
-  LBM_HIP(hipMemcpy(b->d_hdr, &hdr, sizeof hdr, hipMemcpyHostToDevice));
+  const int32_t prev = b->n_cohorts;
+  b->n_cohorts = jets.back().empty() && jets.size() == 1 ? 0 : (int32_t)jets.size();
+  std::vector<BatchHdr> hdr((size_t)b->max_cohorts, BatchHdr{0, {0, 0, 0}});
+  for (int32_t c = 0; c < b->n_cohorts; ++c) {
+    const int32_t n = (int32_t)jets[c].size();
+    hdr[c].njets = n;
+    LBM_HIP(hipMemcpy(b->d_jets + (size_t)c * ms, jets[c].data(), n * sizeof(JetDesc),
+                      hipMemcpyHostToDevice));
+    LBM_HIP(hipMemcpy(b->d_tiles + (size_t)c * (ms + 1), start[c].data(),
+                      start[c].size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  }
+  // cohorts that emptied keep an empty tile list
+  const int32_t zero = 0;
+  for (int32_t c = b->n_cohorts; c < prev; ++c)
+    LBM_HIP(hipMemcpy(b->d_tiles + (size_t)c * (ms + 1), &zero, sizeof zero,
+                      hipMemcpyHostToDevice));
+  const int32_t nh = std::max(prev, b->n_cohorts);
+  if (nh > 0)
+    LBM_HIP(hipMemcpy(b->d_hdr, hdr.data(), nh * sizeof(BatchHdr), hipMemcpyHostToDevice));
   // persistent grid: enough workgroups to fill the chip several times over
   int32_t g = b->wg > 0 ? b->wg : 2048;
   g = (g + 7) / 8 * 8;
@@ -127,18 +157,21 @@ int rebuild(lbm_batch *b) {
   return LBM_OK;
 }
 
-int run_group(lbm_batch *b, int32_t k) {
+int run_group(lbm_batch *b, int32_t k, int32_t c) {
   const int shape = pick_shape(b);
-  auto key = std::make_tuple((int)k, shape, (int)b->grid);
+  const int32_t ms = (int32_t)b->slots.size();
+  auto key = std::make_tuple((int)k, shape, (int)b->grid, (int)c);
   auto it = b->graphs.find(key);
   if (it == b->graphs.end()) {
+    JetDesc *jets = b->d_jets + (size_t)c * ms;
+    const int32_t *tiles = b->d_tiles + (size_t)c * (ms + 1);
+    const BatchHdr *hdr = b->d_hdr + c;
     hipGraph_t g;
     LBM_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
     int rc = LBM_OK;
     for (int32_t q = 0; q < k && !rc; ++q)
-      rc = launch_step(shape, b->prec, b->grid, b->stream, b->d_jets, b->d_tiles, b->d_hdr, q,
-                       b->d_flags);
-    if (!rc) rc = launch_advance(b->stream, b->d_jets, b->d_hdr, (int32_t)b->slots.size(), k);
+      rc = launch_step(shape, b->prec, b->grid, b->stream, jets, tiles, hdr, q, b->d_flags);
+    if (!rc) rc = launch_advance(b->stream, jets, hdr, ms, k);
     const hipError_t e = hipStreamEndCapture(b->stream, &g);
     if (rc || e != hipSuccess) return rc ? rc : LBM_EDEVICE;
     hipGraphExec_t ex;
@@ -173,12 +206,14 @@ int lbm_batch_create(size_t budget_bytes, int32_t max_slots, int32_t precision,
   b->prec = precision;
   b->budget = budget_bytes & ~size_t(255);
   b->slots.resize(max_slots);
+  b->max_cohorts = std::min<int32_t>(max_slots, 64);
   (void)hipGetDevice(&b->device);
+  const size_t mc = (size_t)b->max_cohorts;
   bool ok = hipMalloc(&b->arena_mem, b->budget) == hipSuccess &&
-            hipMalloc(&b->d_jets, max_slots * sizeof(JetDesc)) == hipSuccess &&
+            hipMalloc(&b->d_jets, mc * max_slots * sizeof(JetDesc)) == hipSuccess &&
             hipMalloc(&b->d_slot_desc, max_slots * sizeof(JetDesc)) == hipSuccess &&
-            hipMalloc(&b->d_tiles, (max_slots + 1) * sizeof(int32_t)) == hipSuccess &&
-            hipMalloc(&b->d_hdr, sizeof(BatchHdr)) == hipSuccess &&
+            hipMalloc(&b->d_tiles, mc * (max_slots + 1) * sizeof(int32_t)) == hipSuccess &&
+            hipMalloc(&b->d_hdr, mc * sizeof(BatchHdr)) == hipSuccess &&
             hipMalloc(&b->d_flags, max_slots * sizeof(int32_t)) == hipSuccess;
   if (ok && hip_stream) {
     b->stream = (hipStream_t)hip_stream;
@@ -188,8 +223,14 @@ int lbm_batch_create(size_t budget_bytes, int32_t max_slots, int32_t precision,
   }
   if (ok) {
     std::vector<int32_t> zeros(max_slots, 0);
+    std::vector<BatchHdr> hz(mc, BatchHdr{0, {0, 0, 0}});
+    std::vector<int32_t> tz(mc * (max_slots + 1), 0);
     ok = hipMemcpy(b->d_flags, zeros.data(), max_slots * sizeof(int32_t),
-                   hipMemcpyHostToDevice) == hipSuccess;
+                   hipMemcpyHostToDevice) == hipSuccess &&
+         hipMemcpy(b->d_hdr, hz.data(), mc * sizeof(BatchHdr), hipMemcpyHostToDevice) ==
+             hipSuccess &&
+         hipMemcpy(b->d_tiles, tz.data(), tz.size() * sizeof(int32_t), hipMemcpyHostToDevice) ==
+             hipSuccess;
   }
   if (!ok) {
     lbm_batch_destroy(b);
@@ -294,7 +335,8 @@ int lbm_batch_run(lbm_batch *b, int32_t k_steps) {
   int rc;
   if (b->dirty && (rc = rebuild(b))) return rc;
   if (b->active.empty()) return LBM_OK;
-  if ((rc = run_group(b, k_steps))) return rc;
+  for (int32_t c = 0; c < b->n_cohorts; ++c)
+    if ((rc = run_group(b, k_steps, c))) return rc;
   bool finished = false;
   for (int32_t s : b->active) {
     Slot &sl = b->slots[s];
@@ -382,12 +424,27 @@ int lbm_batch_retire(lbm_batch *b, int32_t slot) {
   return LBM_OK;
 }
 
+int lbm_batch_sync(lbm_batch *b) {
+  if (!b) return LBM_EINVAL;
+  LBM_HIP(hipStreamSynchronize(b->stream));
+  LBM_HIP(hipGetLastError());
+  return LBM_OK;
+}
+
 int lbm_batch_active(const lbm_batch *b, int32_t *n_active, size_t *bytes_used) {
   if (!b) return LBM_EINVAL;
   int32_t n = 0;
   for (const Slot &s : b->slots) n += s.used ? 1 : 0;
   if (n_active) *n_active = n;
   if (bytes_used) *bytes_used = b->used;
+  return LBM_OK;
+}
+
+int lbm_batch_set_cohort_bytes(lbm_batch *b, size_t bytes) {
+  if (!b) return LBM_EINVAL;
+  LBM_HIP(hipStreamSynchronize(b->stream));
+  b->cohort_bytes = bytes;
+  b->dirty = true;
   return LBM_OK;
 }
 

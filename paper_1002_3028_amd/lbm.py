@@ -85,11 +85,13 @@ _SIGS = {
     "lbm_batch_profiles": ([_vp, ctypes.c_int32, _dp, _dp, _dp, _dp], ctypes.c_int),
     "lbm_batch_moments": ([_vp, ctypes.c_int32, _dp, _dp, _dp, _dp], ctypes.c_int),
     "lbm_batch_retire": ([_vp, ctypes.c_int32], ctypes.c_int),
+    "lbm_batch_sync": ([_vp], ctypes.c_int),
     "lbm_batch_jet_bytes": ([_vp, ctypes.POINTER(_Config), ctypes.POINTER(ctypes.c_size_t)],
                             ctypes.c_int),
     "lbm_batch_active": ([_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_size_t)],
                          ctypes.c_int),
     "lbm_batch_set_launch": ([_vp, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
+    "lbm_batch_set_cohort_bytes": ([_vp, ctypes.c_size_t], ctypes.c_int),
     "lbm_batch_destroy": ([_vp], None),
     "lbm_tile_shape_count": ([], ctypes.c_int),
     "lbm_tile_shape": ([ctypes.c_int32] + [ctypes.POINTER(ctypes.c_int32)] * 4, ctypes.c_int),
@@ -401,11 +403,17 @@ class Batch:
         _check(self.lib.lbm_batch_retire(self.b, int(slot)), "lbm_batch_retire")
         self.shapes.pop(slot, None)
 
+    def sync(self):
+        _check(self.lib.lbm_batch_sync(self.b), "lbm_batch_sync")
+
     def active(self):
         n, used = ctypes.c_int32(), ctypes.c_size_t()
         _check(self.lib.lbm_batch_active(self.b, ctypes.byref(n), ctypes.byref(used)),
                "lbm_batch_active")
         return int(n.value), int(used.value)
+
+    def set_cohort_bytes(self, nbytes: int):
+        _check(self.lib.lbm_batch_set_cohort_bytes(self.b, int(nbytes)), "lbm_batch_set_cohort_bytes")
 
     def set_launch(self, tile_shape: int = -1, workgroups: int = 0):
         _check(self.lib.lbm_batch_set_launch(self.b, int(tile_shape), int(workgroups)),

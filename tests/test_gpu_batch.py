@@ -32,11 +32,15 @@ def _moments_after(batch, slots):
     return {s: batch.moments(s) for s in slots}
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp16"])
-def test_alone_equals_in_mix(precision):
+@pytest.mark.parametrize("precision,cohort", [("fp32", 0), ("fp16", 0), ("fp32", 1 << 20),
+                                              ("fp16", 3 << 20)])
+def test_alone_equals_in_mix(precision, cohort):
+    """cohort = 0 puts every jet in one launch; a small cohort limit splits
+    them into several cache-sized cohorts run one after another."""
     from paper_1002_3028_amd import lbm
     jets = _jets()
     with lbm.Batch(1 << 30, 16, precision) as mix:
+        mix.set_cohort_bytes(cohort)
         slots = [mix.admit(p, inlet, steps) for p, inlet, steps in jets]
         for _ in range(12):
             mix.run(10)
