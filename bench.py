@@ -35,7 +35,6 @@ def _ensure_built():
 def read_traffic(name):
     """Per-launch HBM bytes (read + write) from a committed counter summary,
     or None when absent or taken on another version of the kernel source."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
@@ -44,9 +43,8 @@ def read_traffic(name):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    src = b"".join(open(os.path.join(ROOT, "paper_1002_3028_amd", "csrc", f), "rb").read()
-                   for f in ("lbm_device.hpp", "lbm_kernels.hpp"))
-    if vals.get("kernel_source_sha256") != hashlib.sha256(src).hexdigest():
+    from paper_1002_3028_amd.profsum import kernel_source_sha256
+    if vals.get("kernel_source_sha256") != kernel_source_sha256():
         return None
     try:
         return float(vals["hbm_bytes_per_launch"])

@@ -1,0 +1,122 @@
+"""Summaries of rocprofv3 output for the repository's profiles/ folder.
+
+  stats:   per-kernel duration table from a --kernel-trace --stats run
+  traffic: HBM bytes per launch of one kernel from two --pmc runs
+           (FETCH_SIZE, WRITE_SIZE), each scaled by what the same counter
+           reads for the probe's copy of known size.
+
+Both write a short text file that records the command which produced the
+counters and, for traffic, the SHA-256 of the kernel sources it was taken on.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import os
+import statistics
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = ("lbm_device.hpp", "lbm_kernels.hpp")
+
+
+def kernel_source_sha256() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(HERE, "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def _rows(path):
+    with open(path, newline="") as fh:
+        return list(csv.DictReader(fh))
+
+
+def stats(args):
+    rows = _rows(args.csv)
+    lines = [f"# rocprofv3 kernel statistics: {args.title}",
+             f"# command: {args.command}",
+             "# kernel | calls | average us | min us | max us | share %"]
+    for r in rows[: args.top]:
+        name = r["Name"]
+        if len(name) > 110:
+            name = name[:107] + "..."
+        lines.append(f"{name} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.3f} | "
+                     f"{float(r['MinNs']) / 1e3:.3f} | {float(r['MaxNs']) / 1e3:.3f} | "
+                     f"{float(r['Percentage']):.2f}")
+    with open(args.out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
+def _per_kernel(path, counter):
+    out = {}
+    for r in _rows(path):
+        if r["Counter_Name"] != counter:
+            continue
+        out.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]))
+    return out
+
+
+def traffic(args):
+    fetch = _per_kernel(args.fetch, "FETCH_SIZE")
+    write = _per_kernel(args.write, "WRITE_SIZE")
+
+    def pick(d, key):
+        hits = [v for k, v in d.items() if key in k]
+        if not hits:
+            raise SystemExit(f"no dispatch of a kernel matching {key!r}")
+        return [x for v in hits for x in v]
+
+    copy_bytes = args.copy_mib * (1 << 20)
+    f_copy = statistics.median(pick(fetch, "copy_kernel")) * 1024
+    w_copy = statistics.median(pick(write, "copy_kernel")) * 1024
+    f_factor, w_factor = f_copy / copy_bytes, w_copy / copy_bytes
+    f_k = statistics.median(pick(fetch, args.kernel)) * 1024 / f_factor
+    w_k = statistics.median(pick(write, args.kernel)) * 1024 / w_factor
+    alg = args.bytes_per_node * args.nodes
+    lines = [
+        f"# HBM traffic per launch of {args.kernel} ({args.title})",
+        f"# command (fetch): {args.command_fetch}",
+        f"# command (write): {args.command_write}",
+        f"copy_calibration_bytes: {copy_bytes}",
+        f"fetch_factor: {f_factor:.5f}",
+        f"write_factor: {w_factor:.5f}",
+        f"fetch_bytes_per_launch: {f_k:.0f}",
+        f"write_bytes_per_launch: {w_k:.0f}",
+        f"hbm_bytes_per_launch: {f_k + w_k:.0f}",
+        f"algorithmic_bytes_per_launch: {alg}",
+        f"traffic_over_algorithmic: {(f_k + w_k) / alg:.4f}",
+        f"kernel_source_sha256: {kernel_source_sha256()}",
+    ]
+    with open(args.out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    a = sub.add_parser("stats")
+    a.add_argument("--csv", required=True)
+    a.add_argument("--out", required=True)
+    a.add_argument("--title", required=True)
+    a.add_argument("--command", required=True)
+    a.add_argument("--top", type=int, default=12)
+    b = sub.add_parser("traffic")
+    b.add_argument("--fetch", required=True)
+    b.add_argument("--write", required=True)
+    b.add_argument("--kernel", required=True, help="substring of the kernel name")
+    b.add_argument("--copy-mib", type=int, default=256)
+    b.add_argument("--nodes", type=int, required=True)
+    b.add_argument("--bytes-per-node", type=int, required=True)
+    b.add_argument("--out", required=True)
+    b.add_argument("--title", required=True)
+    b.add_argument("--command-fetch", required=True)
+    b.add_argument("--command-write", required=True)
+    args = ap.parse_args()
+    stats(args) if args.cmd == "stats" else traffic(args)
+
+
+if __name__ == "__main__":
+    main()
