@@ -52,12 +52,14 @@ def read_traffic(name):
         return None
 
 
-def time_jet(params, inlet, precision, steps, warmup, graph_steps=50, check_every=1000):
-    """Returns (seconds for `steps` steps, launches, per-launch ms)."""
+def time_jet(params, inlet, precision, steps, warmup, graph_steps=50, check_every=1000,
+             tile_shape=None):
+    """Returns (seconds for `steps` steps, per-launch ms from HIP events on the
+    solver's stream, 3-D mass from the FP64 check)."""
     import torch
     from paper_1002_3028_amd import lbm
 
-    with lbm.Solver(params, precision, graph_steps=graph_steps) as s:
+    with lbm.Solver(params, precision, graph_steps=graph_steps, tile_shape=tile_shape) as s:
         s.set_inlet(*inlet)
         s.step(warmup)
         s.sync()
@@ -71,8 +73,6 @@ def time_jet(params, inlet, precision, steps, warmup, graph_steps=50, check_ever
             n = min(check_every, steps - done)
             s.step(n)
             done += n
-            if done % check_every == 0 or done == steps:
-                pass
         ev1.record(s.torch_stream)
         mass, energy = s.conservation()  # FP64 reduction + stability check (syncs)
         torch.cuda.synchronize()
@@ -149,7 +149,7 @@ def cpu_baseline(params, inlet, budget_s=12.0):
         t = time.perf_counter()
         ref.step(2)
         per = (time.perf_counter() - t) / 2
-        n = int(max(4, min(400, budget_s / per)))
+        n = int(max(4, min(4000, budget_s / per)))
         t = time.perf_counter()
         ref.step(n)
         dt = time.perf_counter() - t
@@ -173,7 +173,7 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_1002_3028_amd import inputs
+    from paper_1002_3028_amd import autotune, inputs, lbm
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     _ensure_built()
@@ -182,7 +182,9 @@ def main():
     nx, nr = 2048, 512
     p, inlet, _ = inputs.workload_single(n_t=20000)
     nodes = nx * nr
-    wall, ms_launch, _ = time_jet(p, inlet, "fp32", args.steps, args.warmup)
+    shapes = lbm.tile_shapes()
+    shape = autotune.best_shape(p, inlet, "fp32")
+    wall, ms_launch, _ = time_jet(p, inlet, "fp32", args.steps, args.warmup, tile_shape=shape)
     glups = nodes * args.steps / wall / 1e9
     achieved = BYTES_PER_NODE["fp32"] * nodes / (ms_launch * 1e-3) / 1e9
     traffic = read_traffic("traffic_step_fp32_2048x512.txt")
@@ -202,7 +204,8 @@ def main():
         "config": {"workload": "single axisymmetric jet, 2048 axial x 512 radial nodes, FP32 "
                                "populations, parabolic inlet R=32 U_max=0.08 with 1% noise, "
                                "T_in=1, C_s=0.17, tau=0.6, property tables seed 1",
-                   "nx": nx, "nr": nr, "precision": "fp32", "graph_steps": 50},
+                   "nx": nx, "nr": nr, "precision": "fp32", "graph_steps": 50,
+                   "tile_shape": list(shapes[shape])},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "bytes_per_node": BYTES_PER_NODE["fp32"],
@@ -212,19 +215,21 @@ def main():
         extra = {}
         steps_x = max(200, args.steps // 4)
         for prec in ("fp16", "bf16"):
-            w, ms, _ = time_jet(p, inlet, prec, steps_x, args.warmup // 2)
+            q = autotune.best_shape(p, inlet, prec)
+            w, ms, _ = time_jet(p, inlet, prec, steps_x, args.warmup // 2, tile_shape=q)
             g = nodes * steps_x / w / 1e9
             extra[f"{prec}_2048x512"] = {
-                "glups": round(g, 3),
+                "glups": round(g, 3), "tile_shape": list(shapes[q]),
                 "hbm_frac": round(BYTES_PER_NODE[prec] * nodes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         pl, inl, _ = inputs.workload_large(n_t=4000)
         nodes_l = pl["nx"] * pl["nr"]
         steps_l = max(100, args.steps // 10)
         for prec in ("fp32", "fp16"):
-            w, ms, _ = time_jet(pl, inl, prec, steps_l, 100)
+            q = autotune.best_shape(pl, inl, prec)
+            w, ms, _ = time_jet(pl, inl, prec, steps_l, 100, tile_shape=q)
             g = nodes_l * steps_l / w / 1e9
             extra[f"{prec}_4096x1024"] = {
-                "glups": round(g, 3),
+                "glups": round(g, 3), "tile_shape": list(shapes[q]),
                 "hbm_frac": round(BYTES_PER_NODE[prec] * nodes_l / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         extra["batch_64_jets"] = bench_batch()
         extra["serving_fp16"] = bench_serving(precision="fp16")

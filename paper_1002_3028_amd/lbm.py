@@ -224,7 +224,7 @@ class Solver:
         _check(rc, "lbm_create_in")
         self.h = h
         del keep
-        if tile_shape is not None:
+        if tile_shape is not None and int(tile_shape) >= 0:
             _check(lib.lbm_set_tile_shape(self.h, int(tile_shape)), "lbm_set_tile_shape")
         if graph_steps:
             _check(lib.lbm_set_graph_steps(self.h, int(graph_steps)), "lbm_set_graph_steps")
