@@ -51,13 +51,16 @@ def property_tables(seed: int, n: int = TABLE_N):
 
 def inlet_rows(nr: int, radius: float, u_max: float, T_in: float = 1.0,
                T_amb: float = 0.0, r0: float = 0.0, n_t: int = 1,
-               noise: float = 0.0, seed: int | None = None):
+               noise: float = 0.0, seed: int | None = None, t_profile: str = "flat"):
     """Inlet rows (ux, ur, T), each (n_t, nr), for the nodes r_j = r0 + j + 1/2.
 
-    Nozzle nodes (r_j < radius) carry u_max (1 - (r_j/radius)^2) and T_in; the
-    rest of the inlet face carries u = 0 and T_amb.  With noise > 0, u is
-    multiplied by (1 + noise * xi), xi ~ N(0, 1) independent per (row, node),
-    drawn from child 2 of SeedSequence(seed).
+    Nozzle nodes (r_j < radius) carry u_max (1 - (r_j/radius)^2) (eq. 7, first
+    line) and, with t_profile = "flat", T_in; with t_profile = "cubic" they
+    carry T_amb + (T_in - T_amb)(1 - (r_j/radius)^3) (eq. 7, second line, with
+    T_min = T_amb and T_max = T_in).  The rest of the inlet face carries u = 0
+    and T_amb.  With noise > 0, u is multiplied by (1 + noise * xi),
+    xi ~ N(0, 1) independent per (row, node), drawn from child 2 of
+    SeedSequence(seed).
     """
     r = r0 + np.arange(nr) + 0.5
     inside = r < radius
@@ -67,7 +70,13 @@ def inlet_rows(nr: int, radius: float, u_max: float, T_in: float = 1.0,
         rng = np.random.default_rng(np.random.SeedSequence(seed).spawn(3)[2])
         ux = ux * (1.0 + noise * rng.standard_normal((n_t, nr)))
     ur = np.zeros((n_t, nr))
-    T = np.tile(np.where(inside, T_in, T_amb), (n_t, 1))
+    if t_profile == "cubic":
+        t_face = np.where(inside, T_amb + (T_in - T_amb) * (1.0 - (r / radius) ** 3), T_amb)
+    elif t_profile == "flat":
+        t_face = np.where(inside, T_in, T_amb)
+    else:
+        raise ValueError(t_profile)
+    T = np.tile(t_face, (n_t, 1))
     return ux, ur, T
 
 
@@ -127,6 +136,21 @@ def batch_jets(n: int = 64, seed: int = 2, steps: int = 5000, hoop: int = 1):
         p["nu_mult"], p["alpha_mult"] = nu_m, al_m
         jets.append((p, inlet_rows(nr, nr / 16.0, u_in, T_in), steps))
     return jets
+
+
+def umax_sweep(u_max_values=(0.03, 0.05, 0.07, 0.09), nx: int = 512, nr: int = 128,
+               steps: int = 3000, hoop: int = 1):
+    """Jets that differ only in the maximum inlet velocity (the paper's Fig. 7
+    setting): inlet radius nr/8, both profiles of eq. (7) (parabolic u, cubic
+    T), T_in = 1 into T = 0, C_s = 0.18, Pr_t = 0.3 (the validation values of
+    Figs. 2-3), tables seed 0."""
+    nu_m, al_m = property_tables(0)
+    out = []
+    for u in u_max_values:
+        p = jet_params(nx, nr, cs=0.18, table_seed=None, hoop=hoop)
+        p["nu_mult"], p["alpha_mult"] = nu_m, al_m
+        out.append((p, inlet_rows(nr, nr / 8.0, u, 1.0, t_profile="cubic"), steps))
+    return out
 
 
 def arrival_trace(n: int = 2000, seed: int = 3, rate: float = 10.0, hoop: int = 1):

@@ -1,0 +1,54 @@
+"""The paper's inlet (both profiles of eq. 7) and its U_max sweep (Fig. 7,
+section 4.1): jets that differ only in the maximum inlet velocity, run
+together in one batch.  The paper states that raising the maximum inlet
+velocity raises the centreline values and moves the velocity fringes
+downstream; both are checked, and each jet is checked against the oracle."""
+import numpy as np
+import pytest
+
+from gpu_common import host_threads, rel_err, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def test_cubic_inlet_temperature_profile():
+    from paper_1002_3028_amd import inputs
+    ux, ur, T = inputs.inlet_rows(64, 16.0, 0.05, 1.0, T_amb=0.2, t_profile="cubic")
+    r = np.arange(64) + 0.5
+    inside = r < 16
+    np.testing.assert_allclose(T[0][inside], 0.2 + 0.8 * (1 - (r[inside] / 16) ** 3))
+    assert np.all(T[0][~inside] == 0.2) and np.all(ur == 0)
+
+
+def test_umax_sweep_batched():
+    import oracle
+    from paper_1002_3028_amd import inputs, lbm
+    jets = inputs.umax_sweep(steps=1500)
+    with lbm.Batch(1 << 30, len(jets), "fp32") as b:
+        slots = [b.admit(p, inlet, steps) for p, inlet, steps in jets]
+        for _ in range(1500 // 50):
+            b.run(50)
+        axis = [b.profiles(s)["ux_axis"] for s in slots]
+        T_axis = [b.profiles(s)["T_axis"] for s in slots]
+    # the fringe u_x = 0.01 on the axis moves downstream with U_max
+    pos = [int(np.argmax(a < 0.01)) for a in axis]
+    assert all(q > p for p, q in zip(pos, pos[1:])), pos
+    # over the developed jet (upstream of the slowest jet's fringe) a higher
+    # U_max gives a higher centreline velocity and temperature
+    dev = slice(1, pos[0])
+    for a, c in zip(axis, axis[1:]):
+        assert np.all(c[dev] > a[dev])
+    for a, c in zip(T_axis, T_axis[1:]):
+        assert np.all(c[dev] >= a[dev])
+    # one jet against the oracle
+    p, inlet, steps = jets[-1]
+    with oracle.RefSolver(p, threads=host_threads()) as r:
+        r.set_inlet(*inlet)
+        r.step(steps)
+        ref = r.profiles()
+    assert rel_err(axis[-1], ref["ux_axis"]) < 1e-3
