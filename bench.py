@@ -4,9 +4,10 @@ A step is one time step of the whole hot path (edge pulls, moments,
 properties, Smagorinsky relaxation time, sources, collision, store) over the
 2048 x 512 jet; the FP64 conservation check runs once per 1000 steps inside
 the timed region.  Throughput is GLUPS (lattice node updates per second /
-1e9); the roofline is HBM bandwidth at 104 B of populations per node update
-for FP32 storage (13 populations read and written) and 52 B for 16-bit
-storage.
+1e9).  The roofline is HBM bandwidth: a launch reads and writes every stored
+population once, 104 B per node for FP32 storage (13 populations) and 52 B
+for 16-bit storage, whether it advances one step or two (the LDS-blocked
+kernel); `achieved` divides those bytes by the measured launch duration.
 
 Prints one JSON line.  Also reports FP16- and BF16-deviation storage on the
 same jet, the 4096 x 1024 jet (a working set above the 256 MB Infinity
@@ -32,6 +33,10 @@ def _ensure_built():
         __graft_entry__.build()
 
 
+def kernel_of(info):
+    return "pair_kernel" if info["steps"] == 2 else "step_kernel"
+
+
 def read_traffic(name):
     """Per-launch HBM bytes (read + write) from a committed counter summary,
     or None when absent or taken on another version of the kernel source."""
@@ -54,7 +59,7 @@ def read_traffic(name):
 
 def time_jet(params, inlet, precision, steps, warmup, graph_steps=50, check_every=1000,
              tile_shape=None):
-    """Returns (seconds for `steps` steps, per-launch ms from HIP events on the
+    """Returns (seconds for `steps` steps, ms per step from HIP events on the
     solver's stream, 3-D mass from the FP64 check)."""
     import torch
     from paper_1002_3028_amd import lbm
@@ -182,12 +187,13 @@ def main():
     nx, nr = 2048, 512
     p, inlet, _ = inputs.workload_single(n_t=20000)
     nodes = nx * nr
-    shapes = lbm.tile_shapes()
     shape = autotune.best_shape(p, inlet, "fp32")
-    wall, ms_launch, _ = time_jet(p, inlet, "fp32", args.steps, args.warmup, tile_shape=shape)
+    info = lbm.tile_shape_info(shape)
+    wall, ms_step, _ = time_jet(p, inlet, "fp32", args.steps, args.warmup, tile_shape=shape)
     glups = nodes * args.steps / wall / 1e9
+    ms_launch = ms_step * info["steps"]
     achieved = BYTES_PER_NODE["fp32"] * nodes / (ms_launch * 1e-3) / 1e9
-    traffic = read_traffic("traffic_step_fp32_2048x512.txt")
+    traffic = read_traffic(f"traffic_{kernel_of(info).split('_')[0]}_fp32_2048x512.txt")
     line = {
         "metric": "GLUPS & % HBM peak, FP32 vs FP16-storage; batched-jet p50/p99 solve latency",
         "value": round(glups, 3),
@@ -205,32 +211,41 @@ def main():
                                "populations, parabolic inlet R=32 U_max=0.08 with 1% noise, "
                                "T_in=1, C_s=0.17, tau=0.6, property tables seed 1",
                    "nx": nx, "nr": nr, "precision": "fp32", "graph_steps": 50,
-                   "tile_shape": list(shapes[shape])},
+                   "tile_shape": info},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "bytes_per_node": BYTES_PER_NODE["fp32"],
-                     "kernel_ms_per_launch": round(ms_launch, 5)},
+                     "traffic": traffic, "kernel": kernel_of(info),
+                     "steps_per_launch": info["steps"],
+                     "bytes_per_node_per_launch": BYTES_PER_NODE["fp32"],
+                     "kernel_ms_per_launch": round(ms_launch, 5),
+                     "per_step_equivalent_GBps": round(
+                         BYTES_PER_NODE["fp32"] * nodes / (ms_step * 1e-3) / 1e9, 1)},
     }
     if not args.no_extra:
         extra = {}
         steps_x = max(200, args.steps // 4)
+
+        def entry(prec, q, w, ms, n_nodes, n_steps):
+            inf = lbm.tile_shape_info(q)
+            return {"glups": round(n_nodes * n_steps / w / 1e9, 3), "tile_shape": inf,
+                    "hbm_frac": round(BYTES_PER_NODE[prec] * n_nodes /
+                                      (ms * inf["steps"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+        # the same jet with one step per launch (the best one-step shape)
+        q1 = autotune.best_shape(p, inlet, "fp32", steps=1)
+        w, ms, _ = time_jet(p, inlet, "fp32", steps_x, args.warmup // 2, tile_shape=q1)
+        extra["fp32_2048x512_one_step"] = entry("fp32", q1, w, ms, nodes, steps_x)
         for prec in ("fp16", "bf16"):
             q = autotune.best_shape(p, inlet, prec)
             w, ms, _ = time_jet(p, inlet, prec, steps_x, args.warmup // 2, tile_shape=q)
-            g = nodes * steps_x / w / 1e9
-            extra[f"{prec}_2048x512"] = {
-                "glups": round(g, 3), "tile_shape": list(shapes[q]),
-                "hbm_frac": round(BYTES_PER_NODE[prec] * nodes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            extra[f"{prec}_2048x512"] = entry(prec, q, w, ms, nodes, steps_x)
         pl, inl, _ = inputs.workload_large(n_t=4000)
         nodes_l = pl["nx"] * pl["nr"]
         steps_l = max(100, args.steps // 10)
         for prec in ("fp32", "fp16"):
             q = autotune.best_shape(pl, inl, prec)
             w, ms, _ = time_jet(pl, inl, prec, steps_l, 100, tile_shape=q)
-            g = nodes_l * steps_l / w / 1e9
-            extra[f"{prec}_4096x1024"] = {
-                "glups": round(g, 3), "tile_shape": list(shapes[q]),
-                "hbm_frac": round(BYTES_PER_NODE[prec] * nodes_l / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            extra[f"{prec}_4096x1024"] = entry(prec, q, w, ms, nodes_l, steps_l)
         extra["batch_64_jets"] = bench_batch()
         extra["serving_fp16"] = bench_serving(precision="fp16")
         extra["serving_fp32"] = bench_serving(precision="fp32")

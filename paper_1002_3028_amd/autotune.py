@@ -1,8 +1,8 @@
 """Launch-shape autotuner for the step kernel.
 
 For a precision and a size class it times every compiled tile shape (block
-shape, nodes per lane, cache policy) on a representative jet and keeps the
-fastest.  Results are cached as JSON keyed by (GPU architecture, precision,
+shape, nodes per lane, cache policy, one or two steps per launch) on a
+representative jet and keeps the fastest.  Results are cached as JSON keyed by (GPU architecture, precision,
 size class) in $LBM_AUTOTUNE_CACHE or ~/.cache/lbmx/autotune.json.
 
 Size classes follow the memory system: the two population buffers either
@@ -63,7 +63,12 @@ def time_shapes(params: dict, inlet, precision: str, steps: int = 200, warmup: i
         if inlet is not None:
             s.set_inlet(*inlet)
         for q in (range(len(lbm.tile_shapes())) if shapes is None else shapes):
-            s.set_tile_shape(q)
+            try:
+                s.set_tile_shape(q)
+            except lbm.LbmError as e:  # two-step shapes refuse periodic jets
+                if e.code != lbm.EINVAL:
+                    raise
+                continue
             s.step(warmup)
             s.sync()
             e0 = torch.cuda.Event(enable_timing=True)
@@ -76,19 +81,27 @@ def time_shapes(params: dict, inlet, precision: str, steps: int = 200, warmup: i
     return out
 
 
-def best_shape(params: dict, inlet, precision: str, retune: bool = False) -> int:
-    """Fastest tile shape for this jet's size class (tuned once, cached)."""
+def best_shape(params: dict, inlet, precision: str, retune: bool = False,
+               steps: int | None = None) -> int:
+    """Fastest tile shape for this jet's size class (tuned once, cached);
+    steps = 1 or 2 restricts the choice to shapes taking that many steps per
+    launch."""
     ws = lbm.bytes_required(params, precision)
     key = f"{_arch()}/{precision}/{size_class(ws)}"
+    periodic = "periodic" in tuple(params.get("bc", ()))[:2]
+    if periodic:
+        key += "/periodic"
+    if steps is not None:
+        key += f"/steps{steps}"
     db = _load()
-    shapes = lbm.tile_shapes()
+    infos = lbm.tile_shape_infos()
     hit = db.get(key)
-    if hit is not None and not retune and tuple(hit.get("shape", ())) in \
-            [tuple(x) for x in shapes]:
-        return [tuple(x) for x in shapes].index(tuple(hit["shape"]))
-    t = time_shapes(params, inlet, precision)
+    if hit is not None and not retune and hit.get("info") in infos:
+        return infos.index(hit["info"])
+    cand = [q for q, inf in enumerate(infos) if steps is None or inf["steps"] == steps]
+    t = time_shapes(params, inlet, precision, shapes=cand)
     q = min(t, key=t.get)
-    db[key] = {"shape": list(shapes[q]), "s_per_step": t[q], "tuned_on": [params["nx"], params["nr"]],
+    db[key] = {"info": infos[q], "s_per_step": t[q], "tuned_on": [params["nx"], params["nr"]],
                "when": time.strftime("%Y-%m-%d %H:%M:%S")}
     _save(db)
     return q

@@ -29,6 +29,9 @@ struct lbm_handle {
   JetDesc desc{};
   int64_t step = 0;  // steps done
   int64_t base = 0;  // step0 held by the device descriptor
+  int32_t flip = 0;  // state after s steps in buf[(s + flip) & 1]; the device
+                     // descriptor holds the same value (two-step launches are
+                     // always followed by an advance)
   int shape = 0;
   int32_t ntiles = 0, grid = 0;
   bool unstable = false;
@@ -41,6 +44,7 @@ namespace {
 
 int upload_desc(lbm_handle *h) {
   h->desc.step0 = h->base;
+  h->desc.flip = h->flip;
   LBM_HIP(hipMemcpyAsync(h->d_desc, &h->desc, sizeof(JetDesc), hipMemcpyHostToDevice, h->stream));
   LBM_HIP(hipStreamSynchronize(h->stream));
   return LBM_OK;
@@ -48,8 +52,9 @@ int upload_desc(lbm_handle *h) {
 
 int set_shape(lbm_handle *h, int shape) {
   int n;
-  tile_shapes(&n);
+  const TileShape *ts = tile_shapes(&n);
   if (shape < 0 || shape >= n) return LBM_EINVAL;
+  if (ts[shape].steps == 2 && has_periodic(&h->cfg)) return LBM_EINVAL;
   int32_t tx;
   h->ntiles = tiles_of(&h->cfg, shape, &tx);
   h->grid = (h->ntiles + 7) / 8 * 8;
@@ -116,7 +121,7 @@ int upload_inlet(lbm_handle *h, const std::vector<float4> &rows, int32_t n_t) {
   int rc = upload_desc(h);
   if (rc) return rc;
   // the inlet ghosts of the current buffer follow the new rows
-  if ((rc = launch_ghost_fill(h->prec, h->stream, h->d_desc, &h->cfg, h->step))) return rc;
+  if ((rc = launch_ghost_fill(h->prec, h->stream, h->d_desc, &h->cfg, h->step, h->flip))) return rc;
   LBM_HIP(hipStreamSynchronize(h->stream));
   return LBM_OK;
 }
@@ -190,7 +195,8 @@ int create_common(const lbm_config *cfg, void *dev_buf, size_t bytes, void *stre
   d.slot = 0;
   std::vector<float4> rows;
   make_inlet(&h->cfg, 0, nullptr, nullptr, nullptr, rows);
-  if ((rc = upload_inlet(h, rows, 1)) || (rc = set_shape(h, default_tile_shape()))) {
+  if ((rc = upload_inlet(h, rows, 1)) ||
+      (rc = set_shape(h, default_tile_shape(h->prec, has_periodic(&h->cfg))))) {
     release(h);
     return rc;
   }
@@ -199,8 +205,8 @@ int create_common(const lbm_config *cfg, void *dev_buf, size_t bytes, void *stre
   const float4 u0 =
       make_float4((float)cfg->rho0, (float)cfg->ux0, (float)cfg->ur0, (float)cfg->T0);
   for (int64_t q = 1; q >= 0 && !rc; --q) {
-    rc = launch_init(h->prec, h->stream, h->d_desc, &h->cfg, q, nullptr, u0);
-    if (!rc) rc = launch_ghost_fill(h->prec, h->stream, h->d_desc, &h->cfg, q);
+    rc = launch_init(h->prec, h->stream, h->d_desc, &h->cfg, q, h->flip, nullptr, u0);
+    if (!rc) rc = launch_ghost_fill(h->prec, h->stream, h->d_desc, &h->cfg, q, h->flip);
   }
   if (rc || hipStreamSynchronize(h->stream) != hipSuccess) {
     release(h);
@@ -210,49 +216,70 @@ int create_common(const lbm_config *cfg, void *dev_buf, size_t bytes, void *stre
   return LBM_OK;
 }
 
+// Capture k steps as one graph: with a two-step shape, k / 2 pair launches
+// (and one single step if k is odd), then the descriptor advance.
+int capture_group(lbm_handle *h, int32_t k, bool pair) {
+  hipGraph_t g;
+  LBM_HIP(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+  int crc = LBM_OK;
+  const int32_t np = pair ? k / 2 : 0;
+  for (int32_t q = 0; q < np && !crc; ++q)
+    crc = launch_step(h->shape, h->prec, h->grid, h->stream, h->d_desc, h->d_tiles, h->d_hdr,
+                      2 * q, q & 1, 2, h->d_flag);
+  for (int32_t q = 2 * np; q < k && !crc; ++q)
+    crc = launch_step(h->shape, h->prec, h->grid, h->stream, h->d_desc, h->d_tiles, h->d_hdr, q,
+                      np & 1, 1, h->d_flag);
+  if (!crc) crc = launch_advance(h->stream, h->d_desc, h->d_hdr, 1, k, np);
+  const hipError_t e = hipStreamEndCapture(h->stream, &g);
+  if (crc || e != hipSuccess) return crc ? crc : LBM_EDEVICE;
+  const hipError_t ei = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (ei != hipSuccess) {
+    h->gexec = nullptr;
+    return LBM_EDEVICE;
+  }
+  h->gexec_k = k;
+  h->gexec_shape = h->shape;
+  return LBM_OK;
+}
+
 int launch_steps(lbm_handle *h, int64_t n) {
+  int nsh;
+  const bool pair = tile_shapes(&nsh)[h->shape].steps == 2;
   int rc;
   while (n > 0) {
+    if (h->base != h->step && (pair || (h->graph_k > 0 && n >= h->graph_k) ||
+                               h->step - h->base > (1 << 30))) {
+      // bring the device step0 to the host count (single steps only since)
+      rc = launch_advance(h->stream, h->d_desc, h->d_hdr, 1, (int32_t)(h->step - h->base), 0);
+      if (rc) return rc;
+      h->base = h->step;
+    }
     if (h->graph_k > 0 && n >= h->graph_k) {
-      if (h->base != h->step) {  // bring the device step0 to the host count
-        rc = launch_advance(h->stream, h->d_desc, h->d_hdr, 1, (int32_t)(h->step - h->base));
-        if (rc) return rc;
-        h->base = h->step;
-      }
       if (!h->gexec || h->gexec_k != h->graph_k || h->gexec_shape != h->shape) {
         drop_graph(h);
-        hipGraph_t g;
-        LBM_HIP(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-        int crc = LBM_OK;
-        for (int32_t k = 0; k < h->graph_k && !crc; ++k)
-          crc = launch_step(h->shape, h->prec, h->grid, h->stream, h->d_desc, h->d_tiles,
-                            h->d_hdr, k, h->d_flag);
-        if (!crc) crc = launch_advance(h->stream, h->d_desc, h->d_hdr, 1, h->graph_k);
-        const hipError_t e = hipStreamEndCapture(h->stream, &g);
-        if (crc || e != hipSuccess) return crc ? crc : LBM_EDEVICE;
-        const hipError_t ei = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(g);
-        if (ei != hipSuccess) {
-          h->gexec = nullptr;
-          return LBM_EDEVICE;
-        }
-        h->gexec_k = h->graph_k;
-        h->gexec_shape = h->shape;
+        if ((rc = capture_group(h, h->graph_k, pair))) return rc;
       }
       LBM_HIP(hipGraphLaunch(h->gexec, h->stream));
       h->step += h->graph_k;
       h->base += h->graph_k;
+      if (pair) h->flip ^= (h->graph_k / 2) & 1;
       n -= h->graph_k;
+    } else if (pair) {
+      // one launch of one or two steps, advanced at once so that the device
+      // descriptor (step0, flip) always matches the host
+      const int32_t m = n >= 2 ? 2 : 1;
+      rc = launch_step(h->shape, h->prec, h->grid, h->stream, h->d_desc, h->d_tiles, h->d_hdr, 0,
+                       0, m, h->d_flag);
+      if (!rc) rc = launch_advance(h->stream, h->d_desc, h->d_hdr, 1, m, m == 2 ? 1 : 0);
+      if (rc) return rc;
+      h->step += m;
+      h->base += m;
+      if (m == 2) h->flip ^= 1;
+      n -= m;
     } else {
-      int64_t koff = h->step - h->base;
-      if (koff > (1 << 30)) {
-        rc = launch_advance(h->stream, h->d_desc, h->d_hdr, 1, (int32_t)koff);
-        if (rc) return rc;
-        h->base = h->step;
-        koff = 0;
-      }
       rc = launch_step(h->shape, h->prec, h->grid, h->stream, h->d_desc, h->d_tiles, h->d_hdr,
-                       (int32_t)koff, h->d_flag);
+                       (int32_t)(h->step - h->base), 0, 1, h->d_flag);
       if (rc) return rc;
       h->step += 1;
       n -= 1;
@@ -333,7 +360,7 @@ int lbm_moments(lbm_handle *h, double *rho, double *ux, double *ur, double *T) {
   void *p;
   int rc = h->scratch.get(nodes * sizeof(float4), &p);
   if (rc) return rc;
-  if ((rc = launch_moments(h->prec, h->stream, h->d_desc, &h->cfg, h->step, (float4 *)p)))
+  if ((rc = launch_moments(h->prec, h->stream, h->d_desc, &h->cfg, h->step, h->flip, (float4 *)p)))
     return rc;
   const int st = sync_and_check(h);
   if (st == LBM_EDEVICE) return st;
@@ -358,7 +385,7 @@ int lbm_profiles(lbm_handle *h, double *ux_axis, double *T_axis, double *ux_exit
   void *p;
   int rc = h->scratch.get(n * sizeof(float2), &p);
   if (rc) return rc;
-  if ((rc = launch_profiles(h->prec, h->stream, h->d_desc, &h->cfg, h->step, (float2 *)p)))
+  if ((rc = launch_profiles(h->prec, h->stream, h->d_desc, &h->cfg, h->step, h->flip, (float2 *)p)))
     return rc;
   const int st = sync_and_check(h);
   if (st == LBM_EDEVICE) return st;
@@ -383,7 +410,7 @@ int lbm_conservation(lbm_handle *h, double *mass3d, double *energy3d) {
   int rc = h->scratch.get((nblocks + 1) * sizeof(RedPartial), &p);
   if (rc) return rc;
   RedPartial *part = (RedPartial *)p;
-  if ((rc = launch_conservation(h->prec, h->stream, h->d_desc, nodes, h->step, part, nblocks,
+  if ((rc = launch_conservation(h->prec, h->stream, h->d_desc, nodes, h->step, h->flip, part, nblocks,
                                 part + nblocks)))
     return rc;
   const int st = sync_and_check(h);
@@ -412,10 +439,10 @@ int lbm_set_state(lbm_handle *h, const double *rho, const double *ux, const doub
   if (rc) return rc;
   LBM_HIP(hipStreamSynchronize(h->stream));
   LBM_HIP(hipMemcpy(p, s.data(), nodes * sizeof(float4), hipMemcpyHostToDevice));
-  if ((rc = launch_init(h->prec, h->stream, h->d_desc, &h->cfg, h->step, (const float4 *)p,
-                        make_float4(0, 0, 0, 0))))
+  if ((rc = launch_init(h->prec, h->stream, h->d_desc, &h->cfg, h->step, h->flip,
+                        (const float4 *)p, make_float4(0, 0, 0, 0))))
     return rc;
-  if ((rc = launch_ghost_fill(h->prec, h->stream, h->d_desc, &h->cfg, h->step))) return rc;
+  if ((rc = launch_ghost_fill(h->prec, h->stream, h->d_desc, &h->cfg, h->step, h->flip))) return rc;
   LBM_HIP(hipStreamSynchronize(h->stream));
   return clear_flag(h);
 }
@@ -426,7 +453,7 @@ int lbm_get_populations(lbm_handle *h, double *f, double *g) {
   void *p;
   int rc = h->scratch.get(NPOP * nodes * sizeof(float), &p);
   if (rc) return rc;
-  if ((rc = launch_decode(h->prec, h->stream, h->d_desc, &h->cfg, h->step, (float *)p)))
+  if ((rc = launch_decode(h->prec, h->stream, h->d_desc, &h->cfg, h->step, h->flip, (float *)p)))
     return rc;
   const int st = sync_and_check(h);
   if (st == LBM_EDEVICE) return st;
@@ -459,9 +486,9 @@ int lbm_set_populations(lbm_handle *h, const double *f, const double *g, int64_t
   h->step = step;
   h->base = step;
   if ((rc = upload_desc(h))) return rc;
-  if ((rc = launch_encode(h->prec, h->stream, h->d_desc, &h->cfg, step, (const float *)p)))
+  if ((rc = launch_encode(h->prec, h->stream, h->d_desc, &h->cfg, step, h->flip, (const float *)p)))
     return rc;
-  if ((rc = launch_ghost_fill(h->prec, h->stream, h->d_desc, &h->cfg, step))) return rc;
+  if ((rc = launch_ghost_fill(h->prec, h->stream, h->d_desc, &h->cfg, step, h->flip))) return rc;
   LBM_HIP(hipStreamSynchronize(h->stream));
   return clear_flag(h);
 }

@@ -27,6 +27,7 @@ struct Slot {
   float4 *d_table = nullptr;
   float4 *d_inlet = nullptr;
   int64_t step = 0, target = 0;
+  int32_t flip = 0;  // state after s steps in buf[(s + flip) & 1]
 };
 
 // First-fit free list over [0, size) with 256-byte granules.
@@ -88,6 +89,7 @@ struct lbm_batch {
   std::vector<int32_t> active;  // slots in the compact list, in order
   bool dirty = true;
   int shape = -1;       // -1: auto
+  int cur_shape = 0;    // shape of the current cohorts (set by rebuild)
   int32_t wg = 0;       // 0: auto
   int32_t grid = 0;
   std::map<std::tuple<int, int, int, int>, hipGraphExec_t> graphs;  // (k, shape, grid, cohort)
@@ -95,7 +97,17 @@ struct lbm_batch {
 
 namespace {
 
-int pick_shape(const lbm_batch *b) { return b->shape >= 0 ? b->shape : default_tile_shape(); }
+// The requested (or default) shape, unless it is a two-step shape and an
+// active jet has periodic edges: then the one-step default.
+int pick_shape(const lbm_batch *b) {
+  const int s = b->shape >= 0 ? b->shape : default_tile_shape(b->prec, false);
+  int n;
+  if (tile_shapes(&n)[s].steps == 2)
+    for (const Slot &sl : b->slots)
+      if (sl.used && sl.step < sl.target && has_periodic(&sl.cfg))
+        return default_tile_shape(b->prec, true);
+  return s;
+}
 
 void drop_graphs(lbm_batch *b) {
   for (auto &kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
@@ -124,6 +136,7 @@ int rebuild(lbm_batch *b) {
     const int nt = tiles_of(&sl.cfg, shape, &tx);
     sl.desc.tiles_x = tx;
     sl.desc.step0 = sl.step;
+    sl.desc.flip = sl.flip;
     jets.back().push_back(sl.desc);
     start.back().push_back(start.back().back() + nt);
     bytes.back() += sl.bytes;
@@ -153,12 +166,15 @@ int rebuild(lbm_batch *b) {
   int32_t g = b->wg > 0 ? b->wg : 2048;
   g = (g + 7) / 8 * 8;
   b->grid = g;
+  b->cur_shape = shape;
   b->dirty = false;
   return LBM_OK;
 }
 
 int run_group(lbm_batch *b, int32_t k, int32_t c) {
-  const int shape = pick_shape(b);
+  const int shape = b->cur_shape;
+  int nsh;
+  const int32_t np = tile_shapes(&nsh)[shape].steps == 2 ? k / 2 : 0;
   const int32_t ms = (int32_t)b->slots.size();
   auto key = std::make_tuple((int)k, shape, (int)b->grid, (int)c);
   auto it = b->graphs.find(key);
@@ -169,9 +185,15 @@ int run_group(lbm_batch *b, int32_t k, int32_t c) {
     hipGraph_t g;
     LBM_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
     int rc = LBM_OK;
-    for (int32_t q = 0; q < k && !rc; ++q)
-      rc = launch_step(shape, b->prec, b->grid, b->stream, jets, tiles, hdr, q, b->d_flags);
-    if (!rc) rc = launch_advance(b->stream, jets, hdr, ms, k);
+    // k / 2 pair launches with a two-step shape (one single step if k is
+    // odd), else k single steps
+    for (int32_t q = 0; q < np && !rc; ++q)
+      rc = launch_step(shape, b->prec, b->grid, b->stream, jets, tiles, hdr, 2 * q, q & 1, 2,
+                       b->d_flags);
+    for (int32_t q = 2 * np; q < k && !rc; ++q)
+      rc = launch_step(shape, b->prec, b->grid, b->stream, jets, tiles, hdr, q, np & 1, 1,
+                       b->d_flags);
+    if (!rc) rc = launch_advance(b->stream, jets, hdr, ms, k, np);
     const hipError_t e = hipStreamEndCapture(b->stream, &g);
     if (rc || e != hipSuccess) return rc ? rc : LBM_EDEVICE;
     hipGraphExec_t ex;
@@ -319,8 +341,8 @@ int lbm_batch_admit(lbm_batch *b, const lbm_config *cfg, int32_t n_t, const doub
   const float4 u0 =
       make_float4((float)cfg->rho0, (float)cfg->ux0, (float)cfg->ur0, (float)cfg->T0);
   for (int64_t q = 1; q >= 0 && !rc; --q) {
-    rc = launch_init(b->prec, b->stream, b->d_slot_desc + s, &sl.cfg, q, nullptr, u0);
-    if (!rc) rc = launch_ghost_fill(b->prec, b->stream, b->d_slot_desc + s, &sl.cfg, q);
+    rc = launch_init(b->prec, b->stream, b->d_slot_desc + s, &sl.cfg, q, 0, nullptr, u0);
+    if (!rc) rc = launch_ghost_fill(b->prec, b->stream, b->d_slot_desc + s, &sl.cfg, q, 0);
   }
   if (rc) return rc;
   b->used += sl.bytes;
@@ -337,9 +359,14 @@ int lbm_batch_run(lbm_batch *b, int32_t k_steps) {
   if (b->active.empty()) return LBM_OK;
   for (int32_t c = 0; c < b->n_cohorts; ++c)
     if ((rc = run_group(b, k_steps, c))) return rc;
+  // mirror of the advance kernel: every pair a jet took in full toggled its flip
+  int nsh;
+  const int64_t np = tile_shapes(&nsh)[b->cur_shape].steps == 2 ? k_steps / 2 : 0;
   bool finished = false;
   for (int32_t s : b->active) {
     Slot &sl = b->slots[s];
+    if (np > 0 && sl.target - sl.step >= 2)
+      sl.flip ^= (int32_t)(std::min<int64_t>(np, (sl.target - sl.step) / 2) & 1);
     sl.step = std::min<int64_t>(sl.step + k_steps, sl.target);
     finished = finished || sl.step >= sl.target;
   }
@@ -370,7 +397,7 @@ int lbm_batch_profiles(lbm_batch *b, int32_t slot, double *ux_axis, double *T_ax
   int rc = b->scratch.get(n * sizeof(float2), &p);
   if (rc) return rc;
   if ((rc = launch_profiles(b->prec, b->stream, b->d_slot_desc + slot, &sl->cfg, sl->step,
-                            (float2 *)p)))
+                            sl->flip, (float2 *)p)))
     return rc;
   int32_t flag;
   if ((rc = slot_flag(b, slot, &flag))) return rc;
@@ -396,7 +423,7 @@ int lbm_batch_moments(lbm_batch *b, int32_t slot, double *rho, double *ux, doubl
   int rc = b->scratch.get(nodes * sizeof(float4), &p);
   if (rc) return rc;
   if ((rc = launch_moments(b->prec, b->stream, b->d_slot_desc + slot, &sl->cfg, sl->step,
-                           (float4 *)p)))
+                           sl->flip, (float4 *)p)))
     return rc;
   int32_t flag;
   if ((rc = slot_flag(b, slot, &flag))) return rc;

@@ -81,7 +81,7 @@ __device__ __forceinline__ gptr<const T> as_global(const T *p) {
 // Per-jet descriptor, read by every kernel through a device pointer.
 // ---------------------------------------------------------------------------
 struct alignas(16) JetDesc {
-  void *buf[2];            // population buffers; state after s steps in buf[s & 1]
+  void *buf[2];            // population buffers; state after s steps in buf[(s + flip) & 1]
   const float4 *table;     // (M_nu, dM_nu, M_alpha, dM_alpha) at each grid point
   const float4 *inlet;     // n_t rows of nr (ux, ur, T, 0)
   int64_t plane;           // elements per population plane (pitch * nr)
@@ -92,7 +92,8 @@ struct alignas(16) JetDesc {
   int32_t bc[4];
   float r0, nu0, alpha0, c18;      // c18 = 18 (C_s Delta)^2
   float inv_prt, G, t_lo, t_scale; // t_scale = (table_n - 1) / (t_hi - t_lo)
-  float rho_ref, g4_ref, one, pad1;  // one = 1.0f, kept opaque to the compiler
+  float rho_ref, g4_ref, one;      // one = 1.0f, kept opaque to the compiler
+  int32_t flip;                    // toggled by every launch that advances two steps
   float wallT[4];                  // NaN: adiabatic
   float eq[4][4];                  // EQ side: rho, ux, ur, T
 };
@@ -184,9 +185,17 @@ __device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sq
 // alpha_tot, the axisymmetric sources, eq. (1) collision.  f and g hold the
 // pulled (pre-collision) populations on entry and f*, g* on exit.  Returns
 // false if rho <= 0 or rho, T are not finite.
+// A hook, if given, is issued right after the property-table gather and
+// nothing is moved across it: a caller can put loads for later work there,
+// behind the gather in the memory counter's order.
 // ---------------------------------------------------------------------------
+struct NoHook {
+  __device__ void operator()() const {}
+};
+
+template <class H = NoHook>
 __device__ __forceinline__ bool collide(const JetDesc &d, float rinv, float r2,
-                                        float (&f)[9], float (&g)[4]) {
+                                        float (&f)[9], float (&g)[4], const H &hook = H()) {
   // eq. (2)
   const float rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
   const float mx = (f[1] + f[5] + f[8]) - (f[3] + f[6] + f[7]);
@@ -195,16 +204,23 @@ __device__ __forceinline__ bool collide(const JetDesc &d, float rinv, float r2,
   const float irho = fast_rcp(rho);
   const float ux = mx * irho, ur = mr * irho;
 
-  // eq. (4): Q_ij = sum_k e_ki e_kj (f_k - f_k^eq).  The equilibrium is
-  // recomputed in the update below rather than kept, to hold fewer registers.
+  // eq. (4): Q_ij = sum_k e_ki e_kj (f_k - f_k^eq)
+  float feq[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) feq[k] = feq_link(k, rho, ux, ur);
+  // (sums start from their first term: no addition of a zero)
   float qxx = 0.f, qrr = 0.f, qxr = 0.f;
+  bool hx = false, hr = false, hxr = false;
 #pragma unroll
   for (int k = 1; k < 9; ++k) {
-    const float fn = f[k] - feq_link(k, rho, ux, ur);
-    if (ex9(k) != 0) qxx += fn;
-    if (er9(k) != 0) qrr += fn;
-    if (ex9(k) * er9(k) > 0) qxr += fn;
-    if (ex9(k) * er9(k) < 0) qxr -= fn;
+    const float fn = f[k] - feq[k];
+    if (ex9(k) != 0) { qxx = hx ? qxx + fn : fn; hx = true; }
+    if (er9(k) != 0) { qrr = hr ? qrr + fn : fn; hr = true; }
+    if (ex9(k) * er9(k) != 0) {
+      const bool pos = ex9(k) * er9(k) > 0;
+      qxr = hxr ? (pos ? qxr + fn : qxr - fn) : (pos ? fn : -fn);
+      hxr = true;
+    }
   }
   // sum_k e_kr g_k^neq (the links +r and -r)
   const float jr = (g[1] - geq_link(1, T, ux, ur)) - (g[3] - geq_link(3, T, ux, ur));
@@ -216,6 +232,11 @@ __device__ __forceinline__ bool collide(const JetDesc &d, float rinv, float r2,
   const float w = x - (float)i0;
   const gptr<const float> tp = as_global((const float *)d.table) + 4 * i0;
   const float4 te = make_float4(tp[0], tp[1], tp[2], tp[3]);
+  if constexpr (!__is_same(H, NoHook)) {
+    __builtin_amdgcn_sched_barrier(0);
+    hook();
+    __builtin_amdgcn_sched_barrier(0);
+  }
   const float nu = d.nu0 * (te.x + w * te.y);
   const float alpha = d.alpha0 * (te.z + w * te.w);
   const float tau_nu = 0.5f + 3.0f * nu;
@@ -242,7 +263,7 @@ __device__ __forceinline__ bool collide(const JetDesc &d, float rinv, float r2,
   const float fx6 = Fx * (1.0f / 6.0f), fr6 = Fr * (1.0f / 6.0f);
 #pragma unroll
   for (int k = 0; k < 9; ++k)
-    f[k] = f[k] - (f[k] - feq_link(k, rho, ux, ur)) * itau +
+    f[k] = f[k] - (f[k] - feq[k]) * itau +
            (w9(k) * theta + proj(ex9(k), er9(k), fx6, fr6));
   const float s4 = 0.25f * S;
 #pragma unroll
@@ -349,13 +370,21 @@ __device__ __forceinline__ float wall_g(const JetDesc &d, int side, float v) {
   return tw == tw ? -v + 0.5f * tw : v;
 }
 
+// Inlet row entry j as (ux, ur, T, 0), read through a global pointer.
+__device__ __forceinline__ float4 inlet_at(const float4 *in, int j) {
+  const gptr<const float> q = as_global((const float *)in) + 4 * j;
+  return make_float4(q[0], q[1], q[2], 0.0f);
+}
+
 // After the collision of node (i, j), write the ghost values of the next
 // step that this node is the source of, following the edge rules (r side
 // first; a mirrored pull goes through the x rule at the edge row).  Ghosts
 // of equilibrium sides are constant and written once by the ghost fill.
 // `in` is the inlet row of the next step.
-template <class C>
-__device__ __forceinline__ void ghost_epilogue(const JetDesc &d, const Dst<C> &o, int i, int j,
+// O is any destination with put(d, p, i, j, v): the next buffer, or the
+// LDS image of the intermediate state of a two-step launch.
+template <class C, class O>
+__device__ __forceinline__ void ghost_epilogue(const JetDesc &d, const O &o, int i, int j,
                                                const float (&f)[9], const float (&g)[4],
                                                const float4 *in) {
   const int nx = d.nx, nr = d.nr;
@@ -390,7 +419,7 @@ __device__ __forceinline__ void ghost_epilogue(const JetDesc &d, const Dst<C> &o
   }
   if (i == 0) {  // ghost column -1 (rows 0..nr-1): links 1, 5, 8 and g0 (+x)
     if (x0 == BC_INLET) {
-      const float4 q = in[j];
+      const float4 q = inlet_at(in, j);
       o.put(d, 1, -1, j, feq_link(1, 1.0f, q.x, q.y));
       o.put(d, 5, -1, j, feq_link(5, 1.0f, q.x, q.y));
       o.put(d, 8, -1, j, feq_link(8, 1.0f, q.x, q.y));
@@ -432,7 +461,10 @@ __device__ __forceinline__ void ghost_epilogue(const JetDesc &d, const Dst<C> &o
   if (j == 0 && mir0) {
     // (-1, -1) link 5 <- x rule of link 8 at column -1, row 0
     if (i == nx - 1 && x0 == BC_PERIODIC) o.put(d, 5, -1, -1, f[8]);
-    if (i == 0 && x0 == BC_INLET) o.put(d, 5, -1, -1, feq_link(8, 1.0f, in[0].x, in[0].y));
+    if (i == 0 && x0 == BC_INLET) {
+      const float4 q = inlet_at(in, 0);
+      o.put(d, 5, -1, -1, feq_link(8, 1.0f, q.x, q.y));
+    }
     if (i == 0 && x0 == BC_WALL) o.put(d, 5, -1, -1, f[6]);
     // (nx, -1) link 6 <- x rule of link 7 at column nx, row 0
     if (i == 0 && x1 == BC_PERIODIC) o.put(d, 6, nx, -1, f[7]);
@@ -442,8 +474,10 @@ __device__ __forceinline__ void ghost_epilogue(const JetDesc &d, const Dst<C> &o
   if (j == nr - 1 && mir1) {
     // (-1, nr) link 8 <- x rule of link 5 at column -1, row nr-1
     if (i == nx - 1 && x0 == BC_PERIODIC) o.put(d, 8, -1, nr, f[5]);
-    if (i == 0 && x0 == BC_INLET)
-      o.put(d, 8, -1, nr, feq_link(5, 1.0f, in[nr - 1].x, in[nr - 1].y));
+    if (i == 0 && x0 == BC_INLET) {
+      const float4 q = inlet_at(in, nr - 1);
+      o.put(d, 8, -1, nr, feq_link(5, 1.0f, q.x, q.y));
+    }
     if (i == 0 && x0 == BC_WALL) o.put(d, 8, -1, nr, f[7]);
     // (nx, nr) link 7 <- x rule of link 6 at column nx, row nr-1
     if (i == 0 && x1 == BC_PERIODIC) o.put(d, 7, nx, nr, f[6]);

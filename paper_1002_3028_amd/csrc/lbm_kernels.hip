@@ -103,7 +103,7 @@ void fill_desc(JetDesc &d, const lbm_config *c) {
   d.rho_ref = (float)c->rho_ref;
   d.g4_ref = (float)(0.25 * c->g_ref);
   d.one = 1.0f;
-  d.pad1 = 0.f;
+  d.flip = 0;
 }
 
 int make_inlet(const lbm_config *c, int32_t n_t, const double *ux, const double *ur,
@@ -125,10 +125,16 @@ int make_inlet(const lbm_config *c, int32_t n_t, const double *ux, const double 
 
 // ---- tile shapes -------------------------------------------------------------
 #define LBM_SHAPE(BX, BY, NY, NX, W, CP)                                         \
-  {BX, BY, NY, NX, W, CP,                                                        \
+  {BX, BY, NY, NX, W, CP, 1, 0,                                                  \
    {(const void *)&step_kernel<CodecF32, BX, BY, NY, NX, W, CP>,                 \
     (const void *)&step_kernel<CodecF16, BX, BY, NY, NX, W, CP>,                 \
     (const void *)&step_kernel<CodecBF16, BX, BY, NY, NX, W, CP>}}
+// two steps per launch: 64 x TY tiles, block 64 x 4
+#define LBM_PAIR(TY, W, CP)                                                      \
+  {64, 4, (TY) / 4, 1, W, CP, 2, NPOP * ((TY) + 2) * PAIR_W * 4,                 \
+   {(const void *)&pair_kernel<CodecF32, TY, W, CP>,                             \
+    (const void *)&pair_kernel<CodecF16, TY, W, CP>,                             \
+    (const void *)&pair_kernel<CodecBF16, TY, W, CP>}}
 
 static const TileShape kShapes[] = {
     LBM_SHAPE(64, 4, 1, 1, 1, 0),  LBM_SHAPE(128, 2, 1, 1, 1, 0), LBM_SHAPE(256, 1, 1, 1, 1, 0),
@@ -136,14 +142,28 @@ static const TileShape kShapes[] = {
     LBM_SHAPE(128, 2, 1, 2, 1, 0), LBM_SHAPE(64, 4, 1, 1, 1, 1),  LBM_SHAPE(64, 4, 1, 1, 1, 2),
     LBM_SHAPE(64, 4, 1, 1, 1, 3),  LBM_SHAPE(64, 4, 2, 1, 1, 1),  LBM_SHAPE(64, 4, 2, 1, 1, 3),
     LBM_SHAPE(128, 2, 1, 1, 1, 1), LBM_SHAPE(64, 8, 2, 1, 1, 0),
+    LBM_PAIR(8, 4, 0),             LBM_PAIR(12, 3, 0),            LBM_PAIR(16, 2, 0),
+    LBM_PAIR(8, 4, 1),             LBM_PAIR(12, 3, 1),            LBM_PAIR(8, 4, 4),
+    LBM_PAIR(12, 3, 4),            LBM_PAIR(8, 4, 5),             LBM_PAIR(16, 2, 4),
 };
 #undef LBM_SHAPE
+#undef LBM_PAIR
 
 const TileShape *tile_shapes(int *count) {
   *count = (int)(sizeof(kShapes) / sizeof(kShapes[0]));
   return kShapes;
 }
-int default_tile_shape() { return 0; }
+// FP32 storage: the two-step kernel on 64 x 8 tiles (the HBM traffic per
+// step halves and the arithmetic still fits under it); 16-bit storage, whose
+// step is arithmetic-limited already, and periodic jets: one step per launch.
+int default_tile_shape(int prec, bool periodic) {
+  if (prec != LBM_PREC_FP32 || periodic) return 0;
+  int n;
+  const TileShape *s = tile_shapes(&n);
+  for (int q = 0; q < n; ++q)
+    if (s[q].steps == 2 && s[q].by * s[q].ny == 8 && s[q].cache == 0) return q;
+  return 0;
+}
 
 int tiles_of(const lbm_config *c, int shape, int32_t *tiles_x) {
   const TileShape &s = kShapes[shape];
@@ -154,92 +174,94 @@ int tiles_of(const lbm_config *c, int shape, int32_t *tiles_x) {
 }
 
 int launch_step(int shape, int prec, int grid, hipStream_t st, const JetDesc *jets,
-                const int32_t *tiles, const BatchHdr *hdr, int32_t koff, int32_t *flags) {
+                const int32_t *tiles, const BatchHdr *hdr, int32_t koff, int32_t tog,
+                int32_t nsteps, int32_t *flags) {
   const TileShape &s = kShapes[shape];
-  void *args[] = {(void *)&jets, (void *)&tiles, (void *)&hdr, (void *)&koff, (void *)&flags};
+  void *args[] = {(void *)&jets, (void *)&tiles, (void *)&hdr,   (void *)&koff,
+                  (void *)&tog,  (void *)&nsteps, (void *)&flags};
   LBM_HIP(hipLaunchKernel(s.fn[codec_index(prec)], dim3(grid), dim3(s.bx, s.by), args, 0, st));
   return LBM_OK;
 }
 
 int launch_advance(hipStream_t st, JetDesc *jets, const BatchHdr *hdr, int32_t njets_max,
-                   int32_t delta) {
+                   int32_t delta, int32_t npair) {
   const int blocks = (njets_max + 63) / 64;
-  hipLaunchKernelGGL(advance_kernel, dim3(blocks), dim3(64), 0, st, jets, hdr, delta);
+  hipLaunchKernelGGL(advance_kernel, dim3(blocks), dim3(64), 0, st, jets, hdr, delta, npair);
   LBM_HIP(hipGetLastError());
   return LBM_OK;
 }
 
 template <class C>
-static void init_t(hipStream_t st, const JetDesc *d, const lbm_config *c, int64_t step,
+static void init_t(hipStream_t st, const JetDesc *d, const lbm_config *c, int64_t step, int32_t flip,
                    const float4 *state, float4 u0) {
   hipLaunchKernelGGL(init_kernel<C>, dim3((c->nx + 255) / 256, c->nr), dim3(256), 0, st, d,
-                     step, state, u0);
+                     step, flip, state, u0);
 }
-int launch_init(int prec, hipStream_t st, const JetDesc *d, const lbm_config *c, int64_t step,
+int launch_init(int prec, hipStream_t st, const JetDesc *d, const lbm_config *c, int64_t step, int32_t flip,
                 const float4 *state, float4 u0) {
-  if (prec == LBM_PREC_FP32) init_t<CodecF32>(st, d, c, step, state, u0);
-  else if (prec == LBM_PREC_FP16DEV) init_t<CodecF16>(st, d, c, step, state, u0);
-  else init_t<CodecBF16>(st, d, c, step, state, u0);
+  if (prec == LBM_PREC_FP32) init_t<CodecF32>(st, d, c, step, flip, state, u0);
+  else if (prec == LBM_PREC_FP16DEV) init_t<CodecF16>(st, d, c, step, flip, state, u0);
+  else init_t<CodecBF16>(st, d, c, step, flip, state, u0);
   LBM_HIP(hipGetLastError());
   return LBM_OK;
 }
 
 template <class C>
-static void ghost_t(hipStream_t st, const JetDesc *d, const lbm_config *c, int64_t step) {
+static void ghost_t(hipStream_t st, const JetDesc *d, const lbm_config *c, int64_t step, int32_t flip) {
   const int n = 2 * (c->nx + 2) + 2 * c->nr;
-  hipLaunchKernelGGL(ghost_fill_kernel<C>, dim3((n + 255) / 256), dim3(256), 0, st, d, step);
+  hipLaunchKernelGGL(ghost_fill_kernel<C>, dim3((n + 255) / 256), dim3(256), 0, st, d, step, flip);
 }
 int launch_ghost_fill(int prec, hipStream_t st, const JetDesc *d, const lbm_config *c,
-                      int64_t step) {
-  if (prec == LBM_PREC_FP32) ghost_t<CodecF32>(st, d, c, step);
-  else if (prec == LBM_PREC_FP16DEV) ghost_t<CodecF16>(st, d, c, step);
-  else ghost_t<CodecBF16>(st, d, c, step);
+                      int64_t step, int32_t flip) {
+  if (prec == LBM_PREC_FP32) ghost_t<CodecF32>(st, d, c, step, flip);
+  else if (prec == LBM_PREC_FP16DEV) ghost_t<CodecF16>(st, d, c, step, flip);
+  else ghost_t<CodecBF16>(st, d, c, step, flip);
   LBM_HIP(hipGetLastError());
   return LBM_OK;
 }
 
 template <class C>
-static void moments_t(hipStream_t st, const JetDesc *d, const lbm_config *c, int64_t step,
+static void moments_t(hipStream_t st, const JetDesc *d, const lbm_config *c, int64_t step, int32_t flip,
                       float4 *out) {
   hipLaunchKernelGGL(moments_kernel<C>, dim3((c->nx + 255) / 256, c->nr), dim3(256), 0, st, d,
-                     step, out);
+                     step, flip, out);
 }
 int launch_moments(int prec, hipStream_t st, const JetDesc *d, const lbm_config *c,
-                   int64_t step, float4 *out) {
-  if (prec == LBM_PREC_FP32) moments_t<CodecF32>(st, d, c, step, out);
-  else if (prec == LBM_PREC_FP16DEV) moments_t<CodecF16>(st, d, c, step, out);
-  else moments_t<CodecBF16>(st, d, c, step, out);
+                   int64_t step, int32_t flip, float4 *out) {
+  if (prec == LBM_PREC_FP32) moments_t<CodecF32>(st, d, c, step, flip, out);
+  else if (prec == LBM_PREC_FP16DEV) moments_t<CodecF16>(st, d, c, step, flip, out);
+  else moments_t<CodecBF16>(st, d, c, step, flip, out);
   LBM_HIP(hipGetLastError());
   return LBM_OK;
 }
 
 template <class C>
-static void profiles_t(hipStream_t st, const JetDesc *d, const lbm_config *c, int64_t step,
+static void profiles_t(hipStream_t st, const JetDesc *d, const lbm_config *c, int64_t step, int32_t flip,
                        float2 *out) {
   const int n = c->nx + c->nr;
-  hipLaunchKernelGGL(profiles_kernel<C>, dim3((n + 255) / 256), dim3(256), 0, st, d, step, out);
+  hipLaunchKernelGGL(profiles_kernel<C>, dim3((n + 255) / 256), dim3(256), 0, st, d, step, flip, out);
 }
 int launch_profiles(int prec, hipStream_t st, const JetDesc *d, const lbm_config *c,
-                    int64_t step, float2 *out) {
-  if (prec == LBM_PREC_FP32) profiles_t<CodecF32>(st, d, c, step, out);
-  else if (prec == LBM_PREC_FP16DEV) profiles_t<CodecF16>(st, d, c, step, out);
-  else profiles_t<CodecBF16>(st, d, c, step, out);
+                    int64_t step, int32_t flip, float2 *out) {
+  if (prec == LBM_PREC_FP32) profiles_t<CodecF32>(st, d, c, step, flip, out);
+  else if (prec == LBM_PREC_FP16DEV) profiles_t<CodecF16>(st, d, c, step, flip, out);
+  else profiles_t<CodecBF16>(st, d, c, step, flip, out);
   LBM_HIP(hipGetLastError());
   return LBM_OK;
 }
 
 template <class C>
-static void cons_t(hipStream_t st, const JetDesc *d, int64_t step, RedPartial *partial,
+static void cons_t(hipStream_t st, const JetDesc *d, int64_t step, int32_t flip, RedPartial *partial,
                    int nblocks) {
-  hipLaunchKernelGGL(conservation_kernel<C>, dim3(nblocks), dim3(RED_THREADS), 0, st, d, step,
+  hipLaunchKernelGGL(conservation_kernel<C>, dim3(nblocks), dim3(RED_THREADS), 0, st, d, step, flip,
                      partial);
 }
-int launch_conservation(int prec, hipStream_t st, const JetDesc *d, int64_t nodes, int64_t step,
+int launch_conservation(int prec, hipStream_t st, const JetDesc *d, int64_t nodes, int64_t step, int32_t flip,
                         RedPartial *partial, int nblocks, RedPartial *out) {
   (void)nodes;
-  if (prec == LBM_PREC_FP32) cons_t<CodecF32>(st, d, step, partial, nblocks);
-  else if (prec == LBM_PREC_FP16DEV) cons_t<CodecF16>(st, d, step, partial, nblocks);
-  else cons_t<CodecBF16>(st, d, step, partial, nblocks);
+  if (prec == LBM_PREC_FP32) cons_t<CodecF32>(st, d, step, flip, partial, nblocks);
+  else if (prec == LBM_PREC_FP16DEV) cons_t<CodecF16>(st, d, step, flip, partial, nblocks);
+  else cons_t<CodecBF16>(st, d, step, flip, partial, nblocks);
   LBM_HIP(hipGetLastError());
   hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(RED_THREADS), 0, st, partial, nblocks,
                      out);
@@ -248,31 +270,31 @@ int launch_conservation(int prec, hipStream_t st, const JetDesc *d, int64_t node
 }
 
 template <class C>
-static void decode_t(hipStream_t st, const JetDesc *d, const lbm_config *c, int64_t step,
+static void decode_t(hipStream_t st, const JetDesc *d, const lbm_config *c, int64_t step, int32_t flip,
                      float *out) {
   hipLaunchKernelGGL(decode_kernel<C>, dim3((c->nx + 255) / 256, c->nr, NPOP), dim3(256), 0, st,
-                     d, step, out);
+                     d, step, flip, out);
 }
-int launch_decode(int prec, hipStream_t st, const JetDesc *d, const lbm_config *c, int64_t step,
+int launch_decode(int prec, hipStream_t st, const JetDesc *d, const lbm_config *c, int64_t step, int32_t flip,
                   float *out) {
-  if (prec == LBM_PREC_FP32) decode_t<CodecF32>(st, d, c, step, out);
-  else if (prec == LBM_PREC_FP16DEV) decode_t<CodecF16>(st, d, c, step, out);
-  else decode_t<CodecBF16>(st, d, c, step, out);
+  if (prec == LBM_PREC_FP32) decode_t<CodecF32>(st, d, c, step, flip, out);
+  else if (prec == LBM_PREC_FP16DEV) decode_t<CodecF16>(st, d, c, step, flip, out);
+  else decode_t<CodecBF16>(st, d, c, step, flip, out);
   LBM_HIP(hipGetLastError());
   return LBM_OK;
 }
 
 template <class C>
-static void encode_t(hipStream_t st, const JetDesc *d, const lbm_config *c, int64_t step,
+static void encode_t(hipStream_t st, const JetDesc *d, const lbm_config *c, int64_t step, int32_t flip,
                      const float *in) {
   hipLaunchKernelGGL(encode_kernel<C>, dim3((c->nx + 255) / 256, c->nr, NPOP), dim3(256), 0, st,
-                     d, step, in);
+                     d, step, flip, in);
 }
-int launch_encode(int prec, hipStream_t st, const JetDesc *d, const lbm_config *c, int64_t step,
+int launch_encode(int prec, hipStream_t st, const JetDesc *d, const lbm_config *c, int64_t step, int32_t flip,
                   const float *in) {
-  if (prec == LBM_PREC_FP32) encode_t<CodecF32>(st, d, c, step, in);
-  else if (prec == LBM_PREC_FP16DEV) encode_t<CodecF16>(st, d, c, step, in);
-  else encode_t<CodecBF16>(st, d, c, step, in);
+  if (prec == LBM_PREC_FP32) encode_t<CodecF32>(st, d, c, step, flip, in);
+  else if (prec == LBM_PREC_FP16DEV) encode_t<CodecF16>(st, d, c, step, flip, in);
+  else encode_t<CodecBF16>(st, d, c, step, flip, in);
   LBM_HIP(hipGetLastError());
   return LBM_OK;
 }
@@ -304,5 +326,15 @@ extern "C" int lbm_tile_shape(int32_t index, int32_t *bx, int32_t *by, int32_t *
   *by = s[index].by;
   *ny = s[index].ny;
   *nx = s[index].nx;
+  return LBM_OK;
+}
+
+extern "C" int lbm_tile_shape_info(int32_t index, int32_t *info, int32_t n) {
+  int count;
+  const lbmx::TileShape *s = lbmx::tile_shapes(&count);
+  if (index < 0 || index >= count || !info || n < 0) return LBM_EINVAL;
+  const lbmx::TileShape &t = s[index];
+  const int32_t v[8] = {t.bx, t.by, t.ny, t.nx, t.waves, t.cache, t.steps, t.lds};
+  for (int32_t q = 0; q < n && q < 8; ++q) info[q] = v[q];
   return LBM_OK;
 }

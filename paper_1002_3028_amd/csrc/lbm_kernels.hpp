@@ -63,13 +63,17 @@ __device__ __forceinline__ T elem(const typename Pack<T, NX>::vec &v, int e) {
 // columns that x-shifted pulls share with the neighbouring tile stay in one
 // L2.  W is the occupancy target (waves per SIMD) for register allocation;
 // CP selects non-temporal stores (bit 0) and loads (bit 1).
-// The jet's state after s steps lives in buf[s & 1]; the step taken here is
-// step0 + koff, skipped once the jet reaches its target.
+// The jet's state after s steps lives in buf[(s + flip) & 1], where flip is
+// the descriptor's value toggled by `tog` (the parity of the two-step
+// launches issued since the descriptor was last advanced); the step taken
+// here is step0 + koff, skipped once the jet reaches its target.  `nsteps`
+// is unused (the two-step kernel below shares this signature).
 // ---------------------------------------------------------------------------
 template <class C, int BX, int BY, int NY, int NX, int W, int CP>
 __global__ __launch_bounds__(BX *BY) __attribute__((amdgpu_waves_per_eu(W, 8))) void step_kernel(
     const JetDesc *__restrict__ jets, const int32_t *__restrict__ tile_start,
-    const BatchHdr *__restrict__ hdr, int32_t koff, int32_t *__restrict__ flags) {
+    const BatchHdr *__restrict__ hdr, int32_t koff, int32_t tog, int32_t nsteps,
+    int32_t *__restrict__ flags) {
   using T = typename C::T;
   constexpr int ES = (int)sizeof(T);
   constexpr int VB = ES * NX;  // bytes per lane per plane
@@ -96,8 +100,9 @@ __global__ __launch_bounds__(BX *BY) __attribute__((amdgpu_waves_per_eu(W, 8))) 
     const int32_t ty = lt / d.tiles_x;
     const int32_t tx = lt - ty * d.tiles_x;
     const int i0 = (tx * BX + (int)threadIdx.x) * NX;
-    T *src_raw = static_cast<T *>(d.buf[step & 1]);
-    T *dst_raw = static_cast<T *>(d.buf[(step + 1) & 1]);
+    const int64_t sel = step + (d.flip ^ tog);
+    T *src_raw = static_cast<T *>(d.buf[sel & 1]);
+    T *dst_raw = static_cast<T *>(d.buf[(sel + 1) & 1]);
     const uint32_t pitch_b = (uint32_t)d.pitch * ES, plane_b = (uint32_t)d.plane * ES;
     const uint32_t span = (uint32_t)NPOP * plane_b;
     const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(src_raw, 0, (int)span, BUF_WORD3);
@@ -173,14 +178,281 @@ __global__ __launch_bounds__(BX *BY) __attribute__((amdgpu_waves_per_eu(W, 8))) 
   }
 }
 
-// Ghost ring of buf[step & 1] from its interior and the inlet row of `step`,
+// ---------------------------------------------------------------------------
+// Node-wise pieces of the two-step kernel (one node per lane).
+// ---------------------------------------------------------------------------
+// The 13 raw storage words node (voff) pulls from a buffer whose ghost ring
+// is current, then their decoded values.  Kept apart so that all 13 loads
+// are in flight before the first is used.
+template <class C, int AUX>
+__device__ __forceinline__ void load_raw(__amdgpu_buffer_rsrc_t rs, uint32_t voff,
+                                         uint32_t plane_b, uint32_t pitch_b,
+                                         typename Raw<sizeof(typename C::T)>::type (&raw)[NPOP]) {
+  constexpr int ES = (int)sizeof(typename C::T);
+#pragma unroll
+  for (int p = 0; p < NPOP; ++p) {
+    const uint32_t soff =
+        (uint32_t)p * plane_b - (uint32_t)(per(p) * (int)pitch_b) - (uint32_t)(pex(p) * ES);
+    raw[p] = buf_load<ES, AUX>(rs, voff, soff);
+  }
+}
+
+template <class C>
+__device__ __forceinline__ void decode_raw(const JetDesc &d,
+                                           const typename Raw<sizeof(typename C::T)>::type (&raw)[NPOP],
+                                           float (&f)[9], float (&g)[4]) {
+  using T = typename C::T;
+#pragma unroll
+  for (int p = 0; p < NPOP; ++p) {
+    const float x = C::dec(__builtin_bit_cast(T, raw[p]), pop_offset<C>(d, p), d.one);
+    if (p < 9) f[p] = x; else g[p - 9] = x;
+  }
+}
+
+template <class C, int AUX>
+__device__ __forceinline__ void load_pulled(const JetDesc &d, __amdgpu_buffer_rsrc_t rs,
+                                            uint32_t voff, uint32_t plane_b, uint32_t pitch_b,
+                                            float (&f)[9], float (&g)[4]) {
+  typename Raw<sizeof(typename C::T)>::type raw[NPOP];
+  load_raw<C, AUX>(rs, voff, plane_b, pitch_b, raw);
+  __builtin_amdgcn_sched_barrier(0);
+  decode_raw<C>(d, raw, f, g);
+}
+
+template <class C, int AUX>
+__device__ __forceinline__ void store_node(const JetDesc &d, __amdgpu_buffer_rsrc_t rd,
+                                           uint32_t voff, uint32_t plane_b, const float (&f)[9],
+                                           const float (&g)[4]) {
+  using T = typename C::T;
+  constexpr int ES = (int)sizeof(T);
+#pragma unroll
+  for (int p = 0; p < NPOP; ++p) {
+    const T x = C::enc(p < 9 ? f[p] : g[p - 9], pop_offset<C>(d, p), d.one);
+    buf_store<ES, AUX>(__builtin_bit_cast(typename Raw<ES>::type, x), rd, voff,
+                       (uint32_t)p * plane_b);
+  }
+}
+
+__device__ __forceinline__ bool is_edge(const JetDesc &d, int i, int j) {
+  return (i == 0) | (i == d.nx - 1) | (j == 0) | (j == d.nr - 1);
+}
+
+// LDS image of the intermediate state of a two-step launch: per plane,
+// EH = TY + 2 rows of PAIR_W = 66 columns, position (x, y) holding node
+// (ia - 1 + x, ja - 1 + y).  Values are kept as the next step would decode
+// them from storage.  put() is the epilogue's destination: writes outside
+// the image are dropped.
+constexpr int PAIR_W = 66;
+
+template <class C, int EH>
+struct LdsImage {
+  float *s;
+  int ia, ja;
+  __device__ __forceinline__ void set(const JetDesc &d, int p, int x, int y, float v) const {
+    const float off = pop_offset<C>(d, p);
+    s[(p * EH + y) * PAIR_W + x] = C::dec(C::enc(v, off, d.one), off, d.one);
+  }
+  __device__ __forceinline__ void put(const JetDesc &d, int p, int i, int j, float v) const {
+    const int x = i - ia + 1, y = j - ja + 1;
+    if (((unsigned)x < (unsigned)PAIR_W) & ((unsigned)y < (unsigned)EH)) set(d, p, x, y, v);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Two steps per launch (temporal blocking).  A workgroup of 64 x 4 threads
+// (one wave per block row) owns a tile of 64 x TY nodes.
+//  1. Every fluid node of the tile and of a one-node frame around it pulls
+//     from the source buffer and collides; the results, and the ghost values
+//     that edge nodes among them produce, go to the LDS image.  With an
+//     equilibrium side, frame positions on the ghost ring first get the
+//     ring's current (constant) values.
+//  2. Every node of the tile pulls from the image, collides and stores to
+//     the other buffer, followed by the ghost epilogue of the next step.
+// Each stored population crosses HBM once per two steps instead of once per
+// step; the frame is computed by both tiles that share it.  The intermediate
+// values are rounded through the storage codec, so the result is
+// bit-identical to two launches of the one-step kernel.
+// After a full pair the state sits in the buffer that the one-step rule
+// assigns to the odd step count, so each full pair toggles the jet's flip:
+// the advance kernel applies it, `tog` accounts for the pairs issued since.
+// A jet one step short of its target (or nsteps == 1) takes one step.
+// Periodic edges are not handled (their ghost values come from the far end
+// of the domain, outside the frame); the runtimes do not select this kernel
+// for such jets.
+// ---------------------------------------------------------------------------
+template <class C, int TY, int W, int CP>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) void pair_kernel(
+    const JetDesc *__restrict__ jets, const int32_t *__restrict__ tile_start,
+    const BatchHdr *__restrict__ hdr, int32_t koff, int32_t tog, int32_t nsteps,
+    int32_t *__restrict__ flags) {
+  using T = typename C::T;
+  constexpr int ES = (int)sizeof(T);
+  constexpr int EH = TY + 2;
+  constexpr int AUX_L = (CP & 2) ? CACHE_NT : 0, AUX_S = (CP & 1) ? CACHE_NT : 0;
+  constexpr bool PF = !(CP & 4);  // bit 2: no prefetch of the next task's loads
+  static_assert(TY % 4 == 0 && 2 * EH <= 64, "tile rows");
+  __shared__ float img[NPOP * EH * PAIR_W];
+  const int lane = (int)threadIdx.x, wave = (int)threadIdx.y;
+  const int32_t njets = hdr->njets;
+  const int32_t ntiles = tile_start[njets];
+  const int32_t G = gridDim.x;  // a multiple of 8
+  const int32_t per_xcd = G >> 3;
+  const int32_t b = blockIdx.x;
+  for (int32_t t = (b & 7) * per_xcd + (b >> 3); t < ntiles; t += G) {
+    int32_t jid = 0;
+    if (njets > 1) {  // last jet whose first tile is <= t
+      int32_t lo = 0, hi = njets - 1;
+      while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (tile_start[mid] <= t) lo = mid; else hi = mid - 1;
+      }
+      jid = lo;
+    }
+    const JetDesc &d = jets[jid];
+    const int64_t step = d.step0 + koff;
+    if (step >= d.target) continue;
+    const bool two = (nsteps > 1) & (step + 1 < d.target);
+    const int32_t lt = t - tile_start[jid];
+    const int32_t ty = lt / d.tiles_x;
+    const int32_t tx = lt - ty * d.tiles_x;
+    const int ia = tx * 64, ja = ty * TY;
+    const int nx = d.nx, nr = d.nr;
+    const int64_t sel = step + (d.flip ^ tog);
+    T *src_raw = static_cast<T *>(d.buf[sel & 1]);
+    T *dst_raw = static_cast<T *>(d.buf[(sel + 1) & 1]);
+    const uint32_t pitch_b = (uint32_t)d.pitch * ES, plane_b = (uint32_t)d.plane * ES;
+    const uint32_t span = (uint32_t)NPOP * plane_b;
+    const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(src_raw, 0, (int)span, BUF_WORD3);
+    const __amdgpu_buffer_rsrc_t rd = __builtin_amdgcn_make_buffer_rsrc(dst_raw, 0, (int)span, BUF_WORD3);
+    const bool tile_edge = (ia == 0) | (ia + 64 >= nx) | (ja == 0) | (ja + TY >= nr);
+    const bool inlet = d.bc[0] == BC_INLET;
+    const float4 *in1 = inlet ? d.inlet + (int64_t)((step + 1) % d.n_t) * nr : d.inlet;
+    const float4 *in2 = inlet ? d.inlet + (int64_t)((step + 2) % d.n_t) * nr : d.inlet;
+    const Dst<C> out{as_global(dst_raw), d.plane, d.pitch};
+    bool ok = true;
+    if (!two) {
+      for (int r = wave; r < TY; r += 4) {
+        const int i = ia + lane, j = ja + r;
+        if ((i < nx) & (j < nr)) {
+          float f[9], g[4];
+          const uint32_t voff = (uint32_t)node_index(d.pitch, i, j) * ES;
+          load_pulled<C, AUX_L>(d, rs, voff, plane_b, pitch_b, f, g);
+          const float rr = d.r0 + (float)j + 0.5f;
+          ok &= collide(d, fast_rcp(rr), rr * rr, f, g);
+          store_node<C, AUX_S>(d, rd, voff, plane_b, f, g);
+          if (is_edge(d, i, j)) ghost_epilogue<C>(d, out, i, j, f, g, in1);
+        }
+      }
+    } else {
+      const LdsImage<C, EH> im{img, ia, ja};
+      // Constant ghosts (equilibrium sides) are never rewritten by the
+      // epilogue: copy the ring positions of the image from the source
+      // buffer first.  Every other ghost value the tile pulls is produced in
+      // step 1 by an edge node of the image.
+      const bool eq_side = (d.bc[0] == BC_EQ) | (d.bc[1] == BC_EQ) | (d.bc[2] == BC_EQ) |
+                           (d.bc[3] == BC_EQ);
+      if (tile_edge & eq_side) {
+        const Src<C> src{as_global(static_cast<const T *>(src_raw)), d.plane, d.pitch};
+        for (int n = lane + 64 * wave; n < EH * PAIR_W; n += 256) {
+          const int y = n / PAIR_W, x = n - y * PAIR_W;
+          const int i = ia - 1 + x, j = ja - 1 + y;
+          const bool ring = (i >= -1) & (i <= nx) & (j >= -1) & (j <= nr) &
+                            ((i == -1) | (i == nx) | (j == -1) | (j == nr));
+          if (ring) {
+            float v[NPOP];
+#pragma unroll
+            for (int p = 0; p < NPOP; ++p) v[p] = src.load(d, p, i, j);
+#pragma unroll
+            for (int p = 0; p < NPOP; ++p) img[(p * EH + y) * PAIR_W + x] = v[p];
+          }
+        }
+      }
+      // step 1: rows 0..EH-1 of the image (columns 1..64), then the two side
+      // columns (0 and 65) as one task of 2 EH lanes: EH + 1 tasks, task q
+      // done by wave q % 4 in round q / 4.  Software pipelined over the
+      // (unrolled) rounds: a wave issues the loads of its next task right
+      // after the property gather of this one.  Positions are clamped into
+      // the domain so that every lane loads valid data; lanes off the fluid
+      // skip the writes.  Every round but the last is valid for every wave.
+      using R = typename Raw<ES>::type;
+      constexpr int NROUND = (EH + 1 + 3) / 4;
+      R raw[2][NPOP];
+      const auto task_xy = [&](int q, int &x, int &y) {
+        x = q < EH ? lane + 1 : ((lane & 1) ? PAIR_W - 1 : 0);
+        y = q < EH ? q : lane >> 1;
+      };
+      // idle lanes of the side task load a row of the image (no new lines)
+      const auto task_voff = [&](int q) {
+        int x, y;
+        task_xy(q, x, y);
+        const int i = min(max(ia - 1 + x, 0), nx - 1);
+        const int j = min(max(ja - 1 + min(y, EH - 1), 0), nr - 1);
+        return (uint32_t)node_index(d.pitch, i, j) * ES;
+      };
+      load_raw<C, AUX_L>(rs, task_voff(wave), plane_b, pitch_b, raw[0]);
+      if (tile_edge & eq_side) __syncthreads();  // ring copy in LDS
+#pragma unroll
+      for (int k = 0; k < NROUND; ++k) {
+        const int q = wave + 4 * k;
+        if (k + 1 < NROUND || q <= EH) {
+          if (!PF && k > 0) {
+            load_raw<C, AUX_L>(rs, task_voff(q), plane_b, pitch_b, raw[k & 1]);
+            __builtin_amdgcn_sched_barrier(0);
+          }
+          const auto prefetch = [&] {
+            if (k + 1 < NROUND)
+              load_raw<C, AUX_L>(rs, task_voff(min(q + 4, EH)), plane_b, pitch_b,
+                                 raw[(k + 1) & 1]);
+          };
+          int x, y;
+          task_xy(q, x, y);
+          const int i = ia - 1 + x, j = ja - 1 + y;
+          float f[9], g[4];
+          decode_raw<C>(d, raw[k & 1], f, g);
+          const float rr = d.r0 + (float)min(max(j, 0), nr - 1) + 0.5f;
+          bool okn;
+          if constexpr (PF) okn = collide(d, fast_rcp(rr), rr * rr, f, g, prefetch);
+          else okn = collide(d, fast_rcp(rr), rr * rr, f, g);
+          if ((y < EH) & (i >= 0) & (i < nx) & (j >= 0) & (j < nr)) {
+            ok &= okn;
+#pragma unroll
+            for (int p = 0; p < NPOP; ++p) im.set(d, p, x, y, p < 9 ? f[p] : g[p - 9]);
+            if (is_edge(d, i, j)) ghost_epilogue<C>(d, im, i, j, f, g, in1);
+          }
+        }
+      }
+      __syncthreads();
+      // step 2: the tile, from the image
+      for (int r = wave; r < TY; r += 4) {
+        const int i = ia + lane, j = ja + r;
+        if ((i < nx) & (j < nr)) {
+          float f[9], g[4];
+#pragma unroll
+          for (int p = 0; p < NPOP; ++p) {
+            const float v = img[(p * EH + r + 1 - per(p)) * PAIR_W + lane + 1 - pex(p)];
+            if (p < 9) f[p] = v; else g[p - 9] = v;
+          }
+          const float rr = d.r0 + (float)j + 0.5f;
+          ok &= collide(d, fast_rcp(rr), rr * rr, f, g);
+          const uint32_t voff = (uint32_t)node_index(d.pitch, i, j) * ES;
+          store_node<C, AUX_S>(d, rd, voff, plane_b, f, g);
+          if (tile_edge && is_edge(d, i, j)) ghost_epilogue<C>(d, out, i, j, f, g, in2);
+        }
+      }
+    }
+    __syncthreads();  // the image is reused by the next tile
+    if (!ok) flags[d.slot] = 1;
+  }
+}
+
+// Ghost ring of buf[(step + flip) & 1] from its interior and the inlet row of `step`,
 // by the pull-side edge rules: every ghost slot (ghost node, link p) whose
 // puller (ghost + e_p) is a fluid node gets the value that node pulls.  Run
 // after any change of the interior or of the inlet made outside the step.
 // One thread per ghost node: row -1 and row nr (nx + 2 each, corners
 // included), then columns -1 and nx (nr each).
 template <class C>
-__global__ void ghost_fill_kernel(const JetDesc *__restrict__ dp, int64_t step) {
+__global__ void ghost_fill_kernel(const JetDesc *__restrict__ dp, int64_t step, int32_t flip) {
   const JetDesc &d = *dp;
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   const int nx = d.nx, nr = d.nr;
@@ -191,7 +463,7 @@ __global__ void ghost_fill_kernel(const JetDesc *__restrict__ dp, int64_t step) 
   else if (q < 2 * (nx + 2) + 2 * nr) { gi = nx; gj = q - 2 * (nx + 2) - nr; }
   else return;
   using T = typename C::T;
-  T *raw = static_cast<T *>(d.buf[step & 1]);
+  T *raw = static_cast<T *>(d.buf[(step + flip) & 1]);
   const Src<C> s{as_global(static_cast<const T *>(raw)), d.plane, d.pitch};
   const Dst<C> o{as_global(raw), d.plane, d.pitch};
   const float4 *inrow = d.inlet + (int64_t)(step % d.n_t) * d.nr;
@@ -204,40 +476,47 @@ __global__ void ghost_fill_kernel(const JetDesc *__restrict__ dp, int64_t step) 
 }
 
 // Moves every jet's step0 by delta (clamped at the target); ends a captured
-// group of steps so that the same graph serves the next group.
+// group of steps so that the same graph serves the next group.  The group
+// began with npair two-step launches: each that a jet took in full (both
+// steps before its target) swapped the roles of its buffers.
 __global__ void advance_kernel(JetDesc *__restrict__ jets, const BatchHdr *__restrict__ hdr,
-                               int32_t delta) {
+                               int32_t delta, int32_t npair) {
   const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q < hdr->njets) {
-    const int64_t s = jets[q].step0 + delta;
-    jets[q].step0 = s < jets[q].target ? s : jets[q].target;
+    const int64_t s0 = jets[q].step0, tg = jets[q].target;
+    if (npair > 0 && tg - s0 >= 2) {
+      const int64_t full = (tg - s0) / 2 < npair ? (tg - s0) / 2 : npair;
+      jets[q].flip ^= (int32_t)(full & 1);
+    }
+    const int64_t s = s0 + delta;
+    jets[q].step0 = s < tg ? s : tg;
   }
 }
 
-// Equilibrium fill of buf[step & 1] from fields (float4 rho, ux, ur, T per
+// Equilibrium fill of buf[(step + flip) & 1] from fields (float4 rho, ux, ur, T per
 // node, i fastest) or, with state == nullptr, from the uniform u0.
 template <class C>
-__global__ void init_kernel(const JetDesc *__restrict__ dp, int64_t step,
+__global__ void init_kernel(const JetDesc *__restrict__ dp, int64_t step, int32_t flip,
                             const float4 *__restrict__ state, float4 u0) {
   const JetDesc &d = *dp;
   const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
   if (i >= d.nx) return;
   const float4 q = state ? state[(int64_t)j * d.nx + i] : u0;
-  typename C::T *o = static_cast<typename C::T *>(d.buf[step & 1]) + node_index(d.pitch, i, j);
+  typename C::T *o = static_cast<typename C::T *>(d.buf[(step + flip) & 1]) + node_index(d.pitch, i, j);
 #pragma unroll
   for (int p = 0; p < NPOP; ++p)
     o[(int64_t)p * d.plane] = C::enc(eq_plane(p, q.x, q.y, q.z, q.w), pop_offset<C>(d, p), d.one);
 }
 
-// Pre-collision moments (eq. 2) of buf[step & 1] at step `step`:
+// Pre-collision moments (eq. 2) of the state after `step` steps:
 // float4 (rho, ux, ur, T) per node, i fastest.
 template <class C>
-__global__ void moments_kernel(const JetDesc *__restrict__ dp, int64_t step,
+__global__ void moments_kernel(const JetDesc *__restrict__ dp, int64_t step, int32_t flip,
                                float4 *__restrict__ out) {
   const JetDesc &d = *dp;
   const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
   if (i >= d.nx) return;
-  Src<C> s{as_global(static_cast<const typename C::T *>(d.buf[step & 1])), d.plane, d.pitch};
+  Src<C> s{as_global(static_cast<const typename C::T *>(d.buf[(step + flip) & 1])), d.plane, d.pitch};
   float f[9], g[4];
   pull_node<C>(d, s, i, j, f, g);
   const float rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
@@ -249,14 +528,14 @@ __global__ void moments_kernel(const JetDesc *__restrict__ dp, int64_t step,
 
 // Centreline (j = 0) and exit column (i = nx-1): (ux, T) pairs, nx + nr.
 template <class C>
-__global__ void profiles_kernel(const JetDesc *__restrict__ dp, int64_t step,
+__global__ void profiles_kernel(const JetDesc *__restrict__ dp, int64_t step, int32_t flip,
                                 float2 *__restrict__ out) {
   const JetDesc &d = *dp;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= d.nx + d.nr) return;
   const int i = t < d.nx ? t : d.nx - 1;
   const int j = t < d.nx ? 0 : t - d.nx;
-  Src<C> s{as_global(static_cast<const typename C::T *>(d.buf[step & 1])), d.plane, d.pitch};
+  Src<C> s{as_global(static_cast<const typename C::T *>(d.buf[(step + flip) & 1])), d.plane, d.pitch};
   float f[9], g[4];
   pull_node<C>(d, s, i, j, f, g);
   const float rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
@@ -272,9 +551,9 @@ __global__ void profiles_kernel(const JetDesc *__restrict__ dp, int64_t step,
 // non-finite rho or T.
 template <class C>
 __global__ __launch_bounds__(RED_THREADS) void conservation_kernel(
-    const JetDesc *__restrict__ dp, int64_t step, RedPartial *__restrict__ partial) {
+    const JetDesc *__restrict__ dp, int64_t step, int32_t flip, RedPartial *__restrict__ partial) {
   const JetDesc &d = *dp;
-  Src<C> s{as_global(static_cast<const typename C::T *>(d.buf[step & 1])), d.plane, d.pitch};
+  Src<C> s{as_global(static_cast<const typename C::T *>(d.buf[(step + flip) & 1])), d.plane, d.pitch};
   const int64_t nodes = (int64_t)d.nx * d.nr;
   double m = 0.0, e = 0.0, bad = 0.0;
   for (int64_t n = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; n < nodes;
@@ -331,23 +610,23 @@ __global__ __launch_bounds__(RED_THREADS) void reduce_partials_kernel(
 
 // Stored populations <-> dense FP32 planes (13 x nr x nx, no pitch).
 template <class C>
-__global__ void decode_kernel(const JetDesc *__restrict__ dp, int64_t step,
+__global__ void decode_kernel(const JetDesc *__restrict__ dp, int64_t step, int32_t flip,
                               float *__restrict__ out) {
   const JetDesc &d = *dp;
   const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y, p = blockIdx.z;
   if (i >= d.nx) return;
-  const typename C::T *b = static_cast<const typename C::T *>(d.buf[step & 1]);
+  const typename C::T *b = static_cast<const typename C::T *>(d.buf[(step + flip) & 1]);
   out[((int64_t)p * d.nr + j) * d.nx + i] =
       C::dec(b[(int64_t)p * d.plane + node_index(d.pitch, i, j)], pop_offset<C>(d, p), d.one);
 }
 
 template <class C>
-__global__ void encode_kernel(const JetDesc *__restrict__ dp, int64_t step,
+__global__ void encode_kernel(const JetDesc *__restrict__ dp, int64_t step, int32_t flip,
                               const float *__restrict__ in) {
   const JetDesc &d = *dp;
   const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y, p = blockIdx.z;
   if (i >= d.nx) return;
-  typename C::T *b = static_cast<typename C::T *>(d.buf[step & 1]);
+  typename C::T *b = static_cast<typename C::T *>(d.buf[(step + flip) & 1]);
   b[(int64_t)p * d.plane + node_index(d.pitch, i, j)] =
       C::enc(in[((int64_t)p * d.nr + j) * d.nx + i], pop_offset<C>(d, p), d.one);
 }

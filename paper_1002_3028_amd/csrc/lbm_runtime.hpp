@@ -42,33 +42,47 @@ int make_inlet(const lbm_config *c, int32_t n_t, const double *ux, const double 
                const double *T, std::vector<float4> &out);
 
 // ---- kernel tables ---------------------------------------------------------
+// A launch variant: block (bx, by), tile (bx * nx) x (by * ny) nodes, the
+// occupancy target, the cache policy, and the steps one launch advances
+// (2: the LDS-blocked two-step kernel, not valid for periodic jets).
 struct TileShape {
-  int bx, by, ny, nx, waves, cache;
+  int bx, by, ny, nx, waves, cache, steps, lds;
   const void *fn[3];  // FP32, FP16-dev, BF16-dev
 };
 const TileShape *tile_shapes(int *count);
-int default_tile_shape();
+int default_tile_shape(int prec, bool periodic);
 
 inline int codec_index(int prec) { return prec - LBM_PREC_FP32; }
 
+inline bool has_periodic(const lbm_config *c) {
+  return c->bc[0] == BC_PERIODIC || c->bc[1] == BC_PERIODIC;
+}
+
+// One launch of tile shape `shape`: the step (or pair) at step0 + koff, with
+// `tog` the parity of two-step launches since the last advance and nsteps
+// (1 or 2) the steps a two-step kernel may take.
 int launch_step(int shape, int prec, int grid, hipStream_t st, const JetDesc *jets,
-                const int32_t *tiles, const BatchHdr *hdr, int32_t koff, int32_t *flags);
+                const int32_t *tiles, const BatchHdr *hdr, int32_t koff, int32_t tog,
+                int32_t nsteps, int32_t *flags);
+// Advance after a group of delta steps whose first npair launches were
+// two-step launches.
 int launch_advance(hipStream_t st, JetDesc *jets, const BatchHdr *hdr, int32_t njets_max,
-                   int32_t delta);
+                   int32_t delta, int32_t npair);
+// Helpers on the state after `step` steps, held in buf[(step + flip) & 1].
 int launch_init(int prec, hipStream_t st, const JetDesc *d, const lbm_config *c, int64_t step,
-                const float4 *state, float4 u0);
+                int32_t flip, const float4 *state, float4 u0);
 int launch_ghost_fill(int prec, hipStream_t st, const JetDesc *d, const lbm_config *c,
-                      int64_t step);
+                      int64_t step, int32_t flip);
 int launch_moments(int prec, hipStream_t st, const JetDesc *d, const lbm_config *c,
-                   int64_t step, float4 *out);
+                   int64_t step, int32_t flip, float4 *out);
 int launch_profiles(int prec, hipStream_t st, const JetDesc *d, const lbm_config *c,
-                    int64_t step, float2 *out);
+                    int64_t step, int32_t flip, float2 *out);
 int launch_conservation(int prec, hipStream_t st, const JetDesc *d, int64_t nodes, int64_t step,
-                        RedPartial *partial, int nblocks, RedPartial *out);
+                        int32_t flip, RedPartial *partial, int nblocks, RedPartial *out);
 int launch_decode(int prec, hipStream_t st, const JetDesc *d, const lbm_config *c, int64_t step,
-                  float *out);
+                  int32_t flip, float *out);
 int launch_encode(int prec, hipStream_t st, const JetDesc *d, const lbm_config *c, int64_t step,
-                  const float *in);
+                  int32_t flip, const float *in);
 
 int tiles_of(const lbm_config *c, int shape, int32_t *tiles_x);
 

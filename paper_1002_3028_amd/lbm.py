@@ -95,6 +95,8 @@ _SIGS = {
     "lbm_batch_destroy": ([_vp], None),
     "lbm_tile_shape_count": ([], ctypes.c_int),
     "lbm_tile_shape": ([ctypes.c_int32] + [ctypes.POINTER(ctypes.c_int32)] * 4, ctypes.c_int),
+    "lbm_tile_shape_info": ([ctypes.c_int32, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32],
+                            ctypes.c_int),
     "lbm_set_tile_shape": ([_vp, ctypes.c_int32], ctypes.c_int),
 }
 
@@ -196,6 +198,20 @@ def tile_shapes():
         _check(lib.lbm_tile_shape(q, *[ctypes.byref(x) for x in v]), "lbm_tile_shape")
         out.append(tuple(x.value for x in v))
     return out
+
+
+SHAPE_FIELDS = ("bx", "by", "ny", "nx", "waves", "cache", "steps", "lds")
+
+
+def tile_shape_info(q: int) -> dict:
+    """Every property of compiled shape q (see lbm_tile_shape_info)."""
+    v = (ctypes.c_int32 * len(SHAPE_FIELDS))()
+    _check(load().lbm_tile_shape_info(int(q), v, len(SHAPE_FIELDS)), "lbm_tile_shape_info")
+    return dict(zip(SHAPE_FIELDS, (int(x) for x in v)))
+
+
+def tile_shape_infos() -> list:
+    return [tile_shape_info(q) for q in range(load().lbm_tile_shape_count())]
 
 
 class Solver:
