@@ -129,12 +129,12 @@ int make_inlet(const lbm_config *c, int32_t n_t, const double *ux, const double 
    {(const void *)&step_kernel<CodecF32, BX, BY, NY, NX, W, CP>,                 \
     (const void *)&step_kernel<CodecF16, BX, BY, NY, NX, W, CP>,                 \
     (const void *)&step_kernel<CodecBF16, BX, BY, NY, NX, W, CP>}}
-// two steps per launch: 64 x TY tiles, block 64 x 4
-#define LBM_PAIR(TY, W, CP)                                                      \
-  {64, 4, (TY) / 4, 1, W, CP, 2, NPOP * ((TY) + 2) * PAIR_W * 4,                 \
-   {(const void *)&pair_kernel<CodecF32, TY, W, CP>,                             \
-    (const void *)&pair_kernel<CodecF16, TY, W, CP>,                             \
-    (const void *)&pair_kernel<CodecBF16, TY, W, CP>}}
+// two steps per launch: 64 x TY tiles, block 64 x NW
+#define LBM_PAIR(TY, NW, W, CP)                                                  \
+  {64, NW, (TY) / (NW), 1, W, CP, 2, NPOP * ((TY) + 2) * PAIR_W * 4,             \
+   {(const void *)&pair_kernel<CodecF32, TY, NW, W, CP>,                         \
+    (const void *)&pair_kernel<CodecF16, TY, NW, W, CP>,                         \
+    (const void *)&pair_kernel<CodecBF16, TY, NW, W, CP>}}
 
 static const TileShape kShapes[] = {
     LBM_SHAPE(64, 4, 1, 1, 1, 0),  LBM_SHAPE(128, 2, 1, 1, 1, 0), LBM_SHAPE(256, 1, 1, 1, 1, 0),
@@ -142,9 +142,9 @@ static const TileShape kShapes[] = {
     LBM_SHAPE(128, 2, 1, 2, 1, 0), LBM_SHAPE(64, 4, 1, 1, 1, 1),  LBM_SHAPE(64, 4, 1, 1, 1, 2),
     LBM_SHAPE(64, 4, 1, 1, 1, 3),  LBM_SHAPE(64, 4, 2, 1, 1, 1),  LBM_SHAPE(64, 4, 2, 1, 1, 3),
     LBM_SHAPE(128, 2, 1, 1, 1, 1), LBM_SHAPE(64, 8, 2, 1, 1, 0),
-    LBM_PAIR(8, 4, 0),             LBM_PAIR(12, 3, 0),            LBM_PAIR(16, 2, 0),
-    LBM_PAIR(8, 4, 1),             LBM_PAIR(12, 3, 1),            LBM_PAIR(8, 4, 4),
-    LBM_PAIR(12, 3, 4),            LBM_PAIR(8, 4, 5),             LBM_PAIR(16, 2, 4),
+    LBM_PAIR(8, 4, 4, 0),          LBM_PAIR(12, 4, 3, 0),         LBM_PAIR(16, 4, 2, 0),
+    LBM_PAIR(8, 4, 4, 1),          LBM_PAIR(12, 4, 3, 1),         LBM_PAIR(8, 4, 4, 4),
+    LBM_PAIR(12, 4, 3, 4),         LBM_PAIR(8, 4, 4, 5),          LBM_PAIR(16, 4, 2, 4),
 };
 #undef LBM_SHAPE
 #undef LBM_PAIR
@@ -161,7 +161,7 @@ int default_tile_shape(int prec, bool periodic) {
   int n;
   const TileShape *s = tile_shapes(&n);
   for (int q = 0; q < n; ++q)
-    if (s[q].steps == 2 && s[q].by * s[q].ny == 8 && s[q].cache == 0) return q;
+    if (s[q].steps == 2 && s[q].by == 4 && s[q].by * s[q].ny == 8 && s[q].cache == 0) return q;
   return 0;
 }
 

@@ -259,8 +259,8 @@ struct LdsImage {
 };
 
 // ---------------------------------------------------------------------------
-// Two steps per launch (temporal blocking).  A workgroup of 64 x 4 threads
-// (one wave per block row) owns a tile of 64 x TY nodes.
+// Two steps per launch (temporal blocking).  A workgroup of 64 x NW threads
+// (NW waves, one per block row) owns a tile of 64 x TY nodes.
 //  1. Every fluid node of the tile and of a one-node frame around it pulls
 //     from the source buffer and collides; the results, and the ghost values
 //     that edge nodes among them produce, go to the LDS image.  With an
@@ -280,8 +280,8 @@ struct LdsImage {
 // of the domain, outside the frame); the runtimes do not select this kernel
 // for such jets.
 // ---------------------------------------------------------------------------
-template <class C, int TY, int W, int CP>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) void pair_kernel(
+template <class C, int TY, int NW, int W, int CP>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(W, 8))) void pair_kernel(
     const JetDesc *__restrict__ jets, const int32_t *__restrict__ tile_start,
     const BatchHdr *__restrict__ hdr, int32_t koff, int32_t tog, int32_t nsteps,
     int32_t *__restrict__ flags) {
@@ -290,7 +290,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
   constexpr int EH = TY + 2;
   constexpr int AUX_L = (CP & 2) ? CACHE_NT : 0, AUX_S = (CP & 1) ? CACHE_NT : 0;
   constexpr bool PF = !(CP & 4);  // bit 2: no prefetch of the next task's loads
-  static_assert(TY % 4 == 0 && 2 * EH <= 64, "tile rows");
+  static_assert(TY % NW == 0 && 2 * EH <= 64, "tile rows");
   __shared__ float img[NPOP * EH * PAIR_W];
   const int lane = (int)threadIdx.x, wave = (int)threadIdx.y;
   const int32_t njets = hdr->njets;
@@ -331,7 +331,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
     const Dst<C> out{as_global(dst_raw), d.plane, d.pitch};
     bool ok = true;
     if (!two) {
-      for (int r = wave; r < TY; r += 4) {
+      for (int r = wave; r < TY; r += NW) {
         const int i = ia + lane, j = ja + r;
         if ((i < nx) & (j < nr)) {
           float f[9], g[4];
@@ -353,7 +353,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
                            (d.bc[3] == BC_EQ);
       if (tile_edge & eq_side) {
         const Src<C> src{as_global(static_cast<const T *>(src_raw)), d.plane, d.pitch};
-        for (int n = lane + 64 * wave; n < EH * PAIR_W; n += 256) {
+        for (int n = lane + 64 * wave; n < EH * PAIR_W; n += 64 * NW) {
           const int y = n / PAIR_W, x = n - y * PAIR_W;
           const int i = ia - 1 + x, j = ja - 1 + y;
           const bool ring = (i >= -1) & (i <= nx) & (j >= -1) & (j <= nr) &
@@ -369,13 +369,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
       }
       // step 1: rows 0..EH-1 of the image (columns 1..64), then the two side
       // columns (0 and 65) as one task of 2 EH lanes: EH + 1 tasks, task q
-      // done by wave q % 4 in round q / 4.  Software pipelined over the
+      // done by wave q % NW in round q / NW.  Software pipelined over the
       // (unrolled) rounds: a wave issues the loads of its next task right
       // after the property gather of this one.  Positions are clamped into
       // the domain so that every lane loads valid data; lanes off the fluid
       // skip the writes.  Every round but the last is valid for every wave.
       using R = typename Raw<ES>::type;
-      constexpr int NROUND = (EH + 1 + 3) / 4;
+      constexpr int NROUND = (EH + NW) / NW;
       R raw[2][NPOP];
       const auto task_xy = [&](int q, int &x, int &y) {
         x = q < EH ? lane + 1 : ((lane & 1) ? PAIR_W - 1 : 0);
@@ -393,7 +393,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
       if (tile_edge & eq_side) __syncthreads();  // ring copy in LDS
 #pragma unroll
       for (int k = 0; k < NROUND; ++k) {
-        const int q = wave + 4 * k;
+        const int q = wave + NW * k;
         if (k + 1 < NROUND || q <= EH) {
           if (!PF && k > 0) {
             load_raw<C, AUX_L>(rs, task_voff(q), plane_b, pitch_b, raw[k & 1]);
@@ -401,7 +401,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
           }
           const auto prefetch = [&] {
             if (k + 1 < NROUND)
-              load_raw<C, AUX_L>(rs, task_voff(min(q + 4, EH)), plane_b, pitch_b,
+              load_raw<C, AUX_L>(rs, task_voff(min(q + NW, EH)), plane_b, pitch_b,
                                  raw[(k + 1) & 1]);
           };
           int x, y;
@@ -423,7 +423,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W, 8))) voi
       }
       __syncthreads();
       // step 2: the tile, from the image
-      for (int r = wave; r < TY; r += 4) {
+      for (int r = wave; r < TY; r += NW) {
         const int i = ia + lane, j = ja + r;
         if ((i < nx) & (j < nr)) {
           float f[9], g[4];
