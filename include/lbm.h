@@ -46,7 +46,7 @@
 extern "C" {
 #endif
 
-#define LBM_ABI_VERSION 1u
+#define LBM_ABI_VERSION 2u
 
 enum lbm_status {
   LBM_OK = 0,
@@ -79,6 +79,14 @@ enum lbm_bc {
   LBM_BC_EQ = 6        /* any side: equilibrium of eq_state[side]           */
 };
 
+/* Population buffers of a jet. */
+enum lbm_layout {
+  LBM_LAYOUT_TWO_BUFFERS = 0, /* read one buffer, write the other each step   */
+  LBM_LAYOUT_SINGLE = 1       /* one buffer updated in place (AA pattern): half
+                                 the memory; one step per launch; results
+                                 bit-identical to the two-buffer layout       */
+};
+
 typedef struct lbm_handle lbm_handle;
 
 typedef struct {
@@ -99,9 +107,11 @@ typedef struct {
   int32_t hoop;               /* 0: explicit hoop term, 1: stabilised         */
   int32_t precision;          /* LBM_PREC_*                                   */
   double rho_ref, g_ref;      /* 16-bit storage offsets (ignored for FP32)    */
+  int32_t layout;             /* LBM_LAYOUT_* (a batch uses its own layout)   */
 } lbm_config;
 
-/* Device bytes lbm_create_in needs for the two population buffers. */
+/* Device bytes lbm_create_in needs for the population buffers (two, or one
+ * with LBM_LAYOUT_SINGLE). */
 int lbm_bytes_required(const lbm_config *cfg, size_t *bytes);
 
 /* Create a solver on the current HIP device, populations at the
@@ -167,8 +177,14 @@ int lbm_probe_copy(void *dst, const void *src, size_t bytes, void *hip_stream);
 typedef struct lbm_batch lbm_batch;
 int lbm_batch_create(size_t budget_bytes, int32_t max_slots, int32_t precision,
                      void *hip_stream, lbm_batch **out);
-/* Admit a jet (cfg->precision is ignored).  LBM_ENOMEM when the budget or the
- * slot table is full.  n_t/ux/ur/T as lbm_set_inlet (n_t = 0: ambient). */
+/* Population layout of every jet of the batch (LBM_LAYOUT_*; default two
+ * buffers).  Only while the batch holds no jet (else LBM_ESTATE).  With
+ * LBM_LAYOUT_SINGLE a jet takes half the budget and every launch advances
+ * one step. */
+int lbm_batch_set_layout(lbm_batch *b, int32_t layout);
+/* Admit a jet (cfg->precision and cfg->layout are ignored).  LBM_ENOMEM when
+ * the budget or the slot table is full.  n_t/ux/ur/T as lbm_set_inlet (n_t = 0:
+ * ambient). */
 int lbm_batch_admit(lbm_batch *b, const lbm_config *cfg, int32_t n_t,
                     const double *ux, const double *ur, const double *T,
                     int64_t target_steps, int32_t *slot);
@@ -207,7 +223,8 @@ int lbm_tile_shape(int32_t index, int32_t *bx, int32_t *by, int32_t *ny, int32_t
  * falls back to the default shape). */
 int lbm_tile_shape_info(int32_t index, int32_t *info, int32_t n);
 /* Select the launch variant of a handle (synchronises; EINVAL for an unknown
- * index or a two-step shape on a periodic configuration). */
+ * index, a two-step shape on a periodic configuration, or any shape but 0 on
+ * a single-buffer handle, whose in-place kernel uses shape 0's tiles). */
 int lbm_set_tile_shape(lbm_handle *h, int32_t index);
 
 #ifdef __cplusplus

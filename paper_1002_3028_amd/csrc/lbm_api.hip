@@ -14,6 +14,7 @@ struct lbm_handle {
   lbm_config cfg{};
   std::vector<double> nu_tab, al_tab;
   int prec = LBM_PREC_FP32;
+  int layout = LBM_LAYOUT_TWO_BUFFERS;
   void *buf = nullptr;
   bool own_buf = false;
   hipStream_t stream = nullptr;
@@ -42,6 +43,10 @@ struct lbm_handle {
 
 namespace {
 
+int32_t view_of(const lbm_handle *h, int64_t step) {
+  return state_view_of(h->layout, step, h->flip);
+}
+
 int upload_desc(lbm_handle *h) {
   h->desc.step0 = h->base;
   h->desc.flip = h->flip;
@@ -55,6 +60,7 @@ int set_shape(lbm_handle *h, int shape) {
   const TileShape *ts = tile_shapes(&n);
   if (shape < 0 || shape >= n) return LBM_EINVAL;
   if (ts[shape].steps == 2 && has_periodic(&h->cfg)) return LBM_EINVAL;
+  if (h->layout == LBM_LAYOUT_SINGLE && shape != 0) return LBM_EINVAL;
   int32_t tx;
   h->ntiles = tiles_of(&h->cfg, shape, &tx);
   h->grid = (h->ntiles + 7) / 8 * 8;
@@ -121,7 +127,7 @@ int upload_inlet(lbm_handle *h, const std::vector<float4> &rows, int32_t n_t) {
   int rc = upload_desc(h);
   if (rc) return rc;
   // the inlet ghosts of the current buffer follow the new rows
-  if ((rc = launch_ghost_fill(h->prec, h->stream, h->d_desc, &h->cfg, h->step, h->flip))) return rc;
+  if ((rc = launch_ghost_fill(h->prec, h->stream, h->d_desc, &h->cfg, h->step, view_of(h, h->step)))) return rc;
   LBM_HIP(hipStreamSynchronize(h->stream));
   return LBM_OK;
 }
@@ -142,20 +148,22 @@ int create_common(const lbm_config *cfg, void *dev_buf, size_t bytes, void *stre
     h->cfg.alpha_mult = h->al_tab.data();
   }
   h->prec = cfg->precision;
+  h->layout = cfg->layout;
   if (hipGetDevice(&h->device) != hipSuccess) {
     release(h);
     return LBM_EDEVICE;
   }
   const size_t one = buffer_bytes(cfg, h->prec);
+  const size_t total = n_buffers(h->layout) * one;
   if (dev_buf) {
-    if (bytes < 2 * one || ((uintptr_t)dev_buf & 255)) {
+    if (bytes < total || ((uintptr_t)dev_buf & 255)) {
       release(h);
       return LBM_EINVAL;
     }
     h->buf = dev_buf;
     h->stream = (hipStream_t)stream;
   } else {
-    if (hipMalloc(&h->buf, 2 * one) != hipSuccess) {
+    if (hipMalloc(&h->buf, total) != hipSuccess) {
       release(h);
       return LBM_ENOMEM;
     }
@@ -189,24 +197,28 @@ int create_common(const lbm_config *cfg, void *dev_buf, size_t bytes, void *stre
   JetDesc &d = h->desc;
   fill_desc(d, &h->cfg);
   d.buf[0] = h->buf;
-  d.buf[1] = (char *)h->buf + one;
+  d.buf[1] = h->layout == LBM_LAYOUT_SINGLE ? h->buf : (char *)h->buf + one;
   d.table = h->d_table;
   d.target = NO_TARGET;
   d.slot = 0;
   std::vector<float4> rows;
   make_inlet(&h->cfg, 0, nullptr, nullptr, nullptr, rows);
   if ((rc = upload_inlet(h, rows, 1)) ||
-      (rc = set_shape(h, default_tile_shape(h->prec, has_periodic(&h->cfg))))) {
+      (rc = set_shape(h, h->layout == LBM_LAYOUT_SINGLE
+                             ? 0
+                             : default_tile_shape(h->prec, has_periodic(&h->cfg))))) {
     release(h);
     return rc;
   }
   // both buffers at the initial equilibrium, each with its ghost ring (the
-  // constant ghosts of equilibrium sides are only ever written here)
+  // constant ghosts of equilibrium sides are only ever written here; the
+  // single buffer's step rewrites them itself)
   const float4 u0 =
       make_float4((float)cfg->rho0, (float)cfg->ux0, (float)cfg->ur0, (float)cfg->T0);
-  for (int64_t q = 1; q >= 0 && !rc; --q) {
-    rc = launch_init(h->prec, h->stream, h->d_desc, &h->cfg, q, h->flip, nullptr, u0);
-    if (!rc) rc = launch_ghost_fill(h->prec, h->stream, h->d_desc, &h->cfg, q, h->flip);
+  for (int64_t q = n_buffers(h->layout) - 1; q >= 0 && !rc; --q) {
+    const int32_t v = view_of(h, q);
+    rc = launch_init(h->prec, h->stream, h->d_desc, &h->cfg, q, v, nullptr, u0);
+    if (!rc) rc = launch_ghost_fill(h->prec, h->stream, h->d_desc, &h->cfg, q, v);
   }
   if (rc || hipStreamSynchronize(h->stream) != hipSuccess) {
     release(h);
@@ -214,6 +226,16 @@ int create_common(const lbm_config *cfg, void *dev_buf, size_t bytes, void *stre
   }
   *out = h;
   return LBM_OK;
+}
+
+// One launch of one step: the in-place kernel for a single buffer, else the
+// handle's shape.
+int one_step(lbm_handle *h, int32_t koff, int32_t tog) {
+  if (h->layout == LBM_LAYOUT_SINGLE)
+    return launch_aa_step(h->prec, h->grid, h->stream, h->d_desc, h->d_tiles, h->d_hdr, koff,
+                          h->d_flag);
+  return launch_step(h->shape, h->prec, h->grid, h->stream, h->d_desc, h->d_tiles, h->d_hdr,
+                     koff, tog, 1, h->d_flag);
 }
 
 // Capture k steps as one graph: with a two-step shape, k / 2 pair launches
@@ -227,8 +249,7 @@ int capture_group(lbm_handle *h, int32_t k, bool pair) {
     crc = launch_step(h->shape, h->prec, h->grid, h->stream, h->d_desc, h->d_tiles, h->d_hdr,
                       2 * q, q & 1, 2, h->d_flag);
   for (int32_t q = 2 * np; q < k && !crc; ++q)
-    crc = launch_step(h->shape, h->prec, h->grid, h->stream, h->d_desc, h->d_tiles, h->d_hdr, q,
-                      np & 1, 1, h->d_flag);
+    crc = one_step(h, q, np & 1);
   if (!crc) crc = launch_advance(h->stream, h->d_desc, h->d_hdr, 1, k, np);
   const hipError_t e = hipStreamEndCapture(h->stream, &g);
   if (crc || e != hipSuccess) return crc ? crc : LBM_EDEVICE;
@@ -278,8 +299,7 @@ int launch_steps(lbm_handle *h, int64_t n) {
       if (m == 2) h->flip ^= 1;
       n -= m;
     } else {
-      rc = launch_step(h->shape, h->prec, h->grid, h->stream, h->d_desc, h->d_tiles, h->d_hdr,
-                       (int32_t)(h->step - h->base), 0, 1, h->d_flag);
+      rc = one_step(h, (int32_t)(h->step - h->base), 0);
       if (rc) return rc;
       h->step += 1;
       n -= 1;
@@ -296,7 +316,7 @@ int lbm_bytes_required(const lbm_config *cfg, size_t *bytes) {
   if (!bytes) return LBM_EINVAL;
   const int rc = validate_config(cfg, true);
   if (rc) return rc;
-  *bytes = 2 * buffer_bytes(cfg, cfg->precision);
+  *bytes = n_buffers(cfg->layout) * buffer_bytes(cfg, cfg->precision);
   return LBM_OK;
 }
 
@@ -360,7 +380,8 @@ int lbm_moments(lbm_handle *h, double *rho, double *ux, double *ur, double *T) {
   void *p;
   int rc = h->scratch.get(nodes * sizeof(float4), &p);
   if (rc) return rc;
-  if ((rc = launch_moments(h->prec, h->stream, h->d_desc, &h->cfg, h->step, h->flip, (float4 *)p)))
+  if ((rc = launch_moments(h->prec, h->stream, h->d_desc, &h->cfg, h->step, view_of(h, h->step),
+                             (float4 *)p)))
     return rc;
   const int st = sync_and_check(h);
   if (st == LBM_EDEVICE) return st;
@@ -385,7 +406,8 @@ int lbm_profiles(lbm_handle *h, double *ux_axis, double *T_axis, double *ux_exit
   void *p;
   int rc = h->scratch.get(n * sizeof(float2), &p);
   if (rc) return rc;
-  if ((rc = launch_profiles(h->prec, h->stream, h->d_desc, &h->cfg, h->step, h->flip, (float2 *)p)))
+  if ((rc = launch_profiles(h->prec, h->stream, h->d_desc, &h->cfg, h->step, view_of(h, h->step),
+                              (float2 *)p)))
     return rc;
   const int st = sync_and_check(h);
   if (st == LBM_EDEVICE) return st;
@@ -410,7 +432,8 @@ int lbm_conservation(lbm_handle *h, double *mass3d, double *energy3d) {
   int rc = h->scratch.get((nblocks + 1) * sizeof(RedPartial), &p);
   if (rc) return rc;
   RedPartial *part = (RedPartial *)p;
-  if ((rc = launch_conservation(h->prec, h->stream, h->d_desc, nodes, h->step, h->flip, part, nblocks,
+  if ((rc = launch_conservation(h->prec, h->stream, h->d_desc, nodes, h->step, view_of(h, h->step),
+                                part, nblocks,
                                 part + nblocks)))
     return rc;
   const int st = sync_and_check(h);
@@ -439,10 +462,10 @@ int lbm_set_state(lbm_handle *h, const double *rho, const double *ux, const doub
   if (rc) return rc;
   LBM_HIP(hipStreamSynchronize(h->stream));
   LBM_HIP(hipMemcpy(p, s.data(), nodes * sizeof(float4), hipMemcpyHostToDevice));
-  if ((rc = launch_init(h->prec, h->stream, h->d_desc, &h->cfg, h->step, h->flip,
+  if ((rc = launch_init(h->prec, h->stream, h->d_desc, &h->cfg, h->step, view_of(h, h->step),
                         (const float4 *)p, make_float4(0, 0, 0, 0))))
     return rc;
-  if ((rc = launch_ghost_fill(h->prec, h->stream, h->d_desc, &h->cfg, h->step, h->flip))) return rc;
+  if ((rc = launch_ghost_fill(h->prec, h->stream, h->d_desc, &h->cfg, h->step, view_of(h, h->step)))) return rc;
   LBM_HIP(hipStreamSynchronize(h->stream));
   return clear_flag(h);
 }
@@ -453,7 +476,8 @@ int lbm_get_populations(lbm_handle *h, double *f, double *g) {
   void *p;
   int rc = h->scratch.get(NPOP * nodes * sizeof(float), &p);
   if (rc) return rc;
-  if ((rc = launch_decode(h->prec, h->stream, h->d_desc, &h->cfg, h->step, h->flip, (float *)p)))
+  if ((rc = launch_decode(h->prec, h->stream, h->d_desc, &h->cfg, h->step, view_of(h, h->step),
+                           (float *)p)))
     return rc;
   const int st = sync_and_check(h);
   if (st == LBM_EDEVICE) return st;
@@ -486,9 +510,10 @@ int lbm_set_populations(lbm_handle *h, const double *f, const double *g, int64_t
   h->step = step;
   h->base = step;
   if ((rc = upload_desc(h))) return rc;
-  if ((rc = launch_encode(h->prec, h->stream, h->d_desc, &h->cfg, step, h->flip, (const float *)p)))
+  if ((rc = launch_encode(h->prec, h->stream, h->d_desc, &h->cfg, step, view_of(h, step),
+                           (const float *)p)))
     return rc;
-  if ((rc = launch_ghost_fill(h->prec, h->stream, h->d_desc, &h->cfg, step, h->flip))) return rc;
+  if ((rc = launch_ghost_fill(h->prec, h->stream, h->d_desc, &h->cfg, step, view_of(h, step)))) return rc;
   LBM_HIP(hipStreamSynchronize(h->stream));
   return clear_flag(h);
 }

@@ -71,6 +71,7 @@ struct Arena {
 struct lbm_batch {
   int device = 0;
   int prec = LBM_PREC_FP32;
+  int layout = LBM_LAYOUT_TWO_BUFFERS;
   hipStream_t stream = nullptr;
   bool own_stream = false;
   size_t budget = 0, used = 0;
@@ -100,6 +101,7 @@ namespace {
 // The requested (or default) shape, unless it is a two-step shape and an
 // active jet has periodic edges: then the one-step default.
 int pick_shape(const lbm_batch *b) {
+  if (b->layout == LBM_LAYOUT_SINGLE) return 0;  // the in-place kernel's tiles
   const int s = b->shape >= 0 ? b->shape : default_tile_shape(b->prec, false);
   int n;
   if (tile_shapes(&n)[s].steps == 2)
@@ -191,8 +193,10 @@ int run_group(lbm_batch *b, int32_t k, int32_t c) {
       rc = launch_step(shape, b->prec, b->grid, b->stream, jets, tiles, hdr, 2 * q, q & 1, 2,
                        b->d_flags);
     for (int32_t q = 2 * np; q < k && !rc; ++q)
-      rc = launch_step(shape, b->prec, b->grid, b->stream, jets, tiles, hdr, q, np & 1, 1,
-                       b->d_flags);
+      rc = b->layout == LBM_LAYOUT_SINGLE
+               ? launch_aa_step(b->prec, b->grid, b->stream, jets, tiles, hdr, q, b->d_flags)
+               : launch_step(shape, b->prec, b->grid, b->stream, jets, tiles, hdr, q, np & 1, 1,
+                             b->d_flags);
     if (!rc) rc = launch_advance(b->stream, jets, hdr, ms, k, np);
     const hipError_t e = hipStreamEndCapture(b->stream, &g);
     if (rc || e != hipSuccess) return rc ? rc : LBM_EDEVICE;
@@ -267,7 +271,18 @@ int lbm_batch_jet_bytes(const lbm_batch *b, const lbm_config *cfg, size_t *bytes
   if (!b || !cfg || !bytes) return LBM_EINVAL;
   const int rc = validate_config(cfg, false);
   if (rc) return rc;
-  *bytes = 2 * buffer_bytes(cfg, b->prec);
+  *bytes = n_buffers(b->layout) * buffer_bytes(cfg, b->prec);
+  return LBM_OK;
+}
+
+int lbm_batch_set_layout(lbm_batch *b, int32_t layout) {
+  if (!b || (layout != LBM_LAYOUT_TWO_BUFFERS && layout != LBM_LAYOUT_SINGLE)) return LBM_EINVAL;
+  for (const Slot &s : b->slots)
+    if (s.used) return LBM_ESTATE;
+  LBM_HIP(hipStreamSynchronize(b->stream));
+  b->layout = layout;
+  b->dirty = true;
+  drop_graphs(b);
   return LBM_OK;
 }
 
@@ -285,12 +300,14 @@ int lbm_batch_admit(lbm_batch *b, const lbm_config *cfg, int32_t n_t, const doub
     }
   if (s < 0) return LBM_ENOMEM;
   const size_t one = buffer_bytes(cfg, b->prec);
+  const size_t need = n_buffers(b->layout) * one;
   size_t off;
-  if (!b->arena.alloc(2 * one, &off)) return LBM_ENOMEM;
+  if (!b->arena.alloc(need, &off)) return LBM_ENOMEM;
   Slot &sl = b->slots[s];
   sl = Slot();
   sl.cfg = *cfg;
   sl.cfg.precision = b->prec;
+  sl.cfg.layout = b->layout;
   if (cfg->table_n > 0) {
     sl.nu_tab.assign(cfg->nu_mult, cfg->nu_mult + cfg->table_n);
     sl.al_tab.assign(cfg->alpha_mult, cfg->alpha_mult + cfg->table_n);
@@ -299,7 +316,7 @@ int lbm_batch_admit(lbm_batch *b, const lbm_config *cfg, int32_t n_t, const doub
   }
   std::vector<float4> rows;
   if ((rc = make_inlet(&sl.cfg, n_t, ux, ur, T, rows))) {
-    b->arena.release(off, 2 * one);
+    b->arena.release(off, need);
     return rc;
   }
   std::vector<float4> table = make_table(&sl.cfg);
@@ -312,19 +329,19 @@ int lbm_batch_admit(lbm_batch *b, const lbm_config *cfg, int32_t n_t, const doub
   if (!ok) {
     if (sl.d_table) (void)hipFree(sl.d_table);
     if (sl.d_inlet) (void)hipFree(sl.d_inlet);
-    b->arena.release(off, 2 * one);
+    b->arena.release(off, need);
     sl = Slot();
     return LBM_ENOMEM;
   }
   sl.used = true;
   sl.off = off;
-  sl.bytes = 2 * one;
+  sl.bytes = need;
   sl.step = 0;
   sl.target = target_steps;
   JetDesc &d = sl.desc;
   fill_desc(d, &sl.cfg);
   d.buf[0] = (char *)b->arena_mem + off;
-  d.buf[1] = (char *)b->arena_mem + off + one;
+  d.buf[1] = b->layout == LBM_LAYOUT_SINGLE ? d.buf[0] : (char *)b->arena_mem + off + one;
   d.table = sl.d_table;
   d.inlet = sl.d_inlet;
   d.n_t = n_t == 0 ? 1 : n_t;
@@ -340,9 +357,10 @@ int lbm_batch_admit(lbm_batch *b, const lbm_config *cfg, int32_t n_t, const doub
   LBM_HIP(hipMemcpy(b->d_flags + s, &zero, sizeof zero, hipMemcpyHostToDevice));
   const float4 u0 =
       make_float4((float)cfg->rho0, (float)cfg->ux0, (float)cfg->ur0, (float)cfg->T0);
-  for (int64_t q = 1; q >= 0 && !rc; --q) {
-    rc = launch_init(b->prec, b->stream, b->d_slot_desc + s, &sl.cfg, q, 0, nullptr, u0);
-    if (!rc) rc = launch_ghost_fill(b->prec, b->stream, b->d_slot_desc + s, &sl.cfg, q, 0);
+  for (int64_t q = n_buffers(b->layout) - 1; q >= 0 && !rc; --q) {
+    const int32_t v = state_view_of(b->layout, q, 0);
+    rc = launch_init(b->prec, b->stream, b->d_slot_desc + s, &sl.cfg, q, v, nullptr, u0);
+    if (!rc) rc = launch_ghost_fill(b->prec, b->stream, b->d_slot_desc + s, &sl.cfg, q, v);
   }
   if (rc) return rc;
   b->used += sl.bytes;
@@ -397,7 +415,7 @@ int lbm_batch_profiles(lbm_batch *b, int32_t slot, double *ux_axis, double *T_ax
   int rc = b->scratch.get(n * sizeof(float2), &p);
   if (rc) return rc;
   if ((rc = launch_profiles(b->prec, b->stream, b->d_slot_desc + slot, &sl->cfg, sl->step,
-                            sl->flip, (float2 *)p)))
+                            state_view_of(b->layout, sl->step, sl->flip), (float2 *)p)))
     return rc;
   int32_t flag;
   if ((rc = slot_flag(b, slot, &flag))) return rc;
@@ -423,7 +441,7 @@ int lbm_batch_moments(lbm_batch *b, int32_t slot, double *rho, double *ux, doubl
   int rc = b->scratch.get(nodes * sizeof(float4), &p);
   if (rc) return rc;
   if ((rc = launch_moments(b->prec, b->stream, b->d_slot_desc + slot, &sl->cfg, sl->step,
-                           sl->flip, (float4 *)p)))
+                           state_view_of(b->layout, sl->step, sl->flip), (float4 *)p)))
     return rc;
   int32_t flag;
   if ((rc = slot_flag(b, slot, &flag))) return rc;

@@ -297,8 +297,8 @@ struct Dst {
 
 // x-side rule for plane p taken from column ip of row jr; (i_land, j_land)
 // is the receiving node (for a mirrored pull, the node of the edge row).
-template <class C>
-__device__ __forceinline__ float pull_x(const JetDesc &d, const Src<C> &s, int p, int ip,
+template <class C, class S>
+__device__ __forceinline__ float pull_x(const JetDesc &d, const S &s, int p, int ip,
                                         int jr, int i_land, int j_land, const float4 *inrow) {
   if (ip >= 0 && ip < d.nx) return s.load(d, p, ip, jr);
   const int side = ip < 0 ? 0 : 1;
@@ -328,17 +328,17 @@ __device__ __forceinline__ float pull_x(const JetDesc &d, const Src<C> &s, int p
 
 // Value pulled by node (i, j) along plane p when the source node lies outside
 // the domain (or may): r-side rule first, then the x-side rule.
-template <class C>
-__device__ __forceinline__ float pull_edge(const JetDesc &d, const Src<C> &s, int p, int i,
+template <class C, class S>
+__device__ __forceinline__ float pull_edge(const JetDesc &d, const S &s, int p, int i,
                                            int j, const float4 *inrow) {
   const int ip = i - pex(p), jp = j - per(p);
-  if (jp >= 0 && jp < d.nr) return pull_x<C>(d, s, p, ip, jp, i, j, inrow);
+  if (jp >= 0 && jp < d.nr) return pull_x<C, S>(d, s, p, ip, jp, i, j, inrow);
   const int side = jp < 0 ? 2 : 3;
   const int bc = d.bc[side];
   if (bc == BC_AXIS || bc == BC_FREESLIP) {
     const int pm = p < 9 ? mir9(p) : 9 + mir4(p - 9);
     const int je = jp < 0 ? 0 : d.nr - 1;
-    return pull_x<C>(d, s, pm, ip, je, i, je, inrow);
+    return pull_x<C, S>(d, s, pm, ip, je, i, je, inrow);
   }
   if (bc == BC_WALL) {
     const int po = p < 9 ? opp9(p) : 9 + opp4(p - 9);
@@ -353,14 +353,104 @@ __device__ __forceinline__ float pull_edge(const JetDesc &d, const Src<C> &s, in
 
 // All 13 pulled values of node (i, j) from a buffer whose ghost ring is
 // current: every pull is a plain load.
-template <class C>
-__device__ __forceinline__ void pull_node(const JetDesc &d, const Src<C> &s, int i, int j,
+template <class C, class S>
+__device__ __forceinline__ void pull_node(const JetDesc &d, const S &s, int i, int j,
                                           float (&f)[9], float (&g)[4]) {
 #pragma unroll
   for (int p = 0; p < NPOP; ++p) {
     const float v = s.load(d, p, i - pex(p), j - per(p));
     if (p < 9) f[p] = v; else g[p - 9] = v;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Views of a stored state.  In the two-buffer scheme a buffer holds, at a
+// fluid node y and plane p, the post-collision value f*_p(y) of the last
+// step, and at a ghost position g the value that node g + e_p pulls along p.
+// The single-buffer (AA) scheme keeps one buffer in one of two layouts:
+//   swapped (after an even number of steps): the two-buffer array with
+//     planes p and opp(p) exchanged, f*_p(y) in plane opp(p) at y;
+//   natural (after an odd number of steps): every population already
+//     streamed, plane p at node x holding the value x pulls along p.
+// A step from the swapped layout pulls from the neighbours and pushes to
+// them; a step from the natural layout reads and writes only its own node.
+// In both, every location is read and written by one thread, so a single
+// buffer suffices.
+//   load(p, i, j):      the two-buffer value at (i, j);
+//   put(p, i, j, v):    write it (for a ghost position: the value pulled by
+//                       (i, j) + e_p along p), i.e. the epilogue's and the
+//                       ghost fill's destination;
+//   pulled(p, i, j):    the value fluid node (i, j) pulls along p.
+// view: 0, 1 = buffer 0 or 1 of the two-buffer scheme; 2 = swapped,
+// 3 = natural layout of the single buffer (buf[0]).
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int opp_plane(int p) { return p < 9 ? opp9(p) : 9 + opp4(p - 9); }
+
+template <class C>
+struct State {
+  using T = typename C::T;
+  gptr<T> base;
+  int64_t plane;
+  int32_t pitch;
+  int32_t kind;  // 0: two-buffer, 1: swapped, 2: natural
+  __device__ __forceinline__ gptr<T> at(int p, int i, int j) const {
+    if (kind == 1) p = opp_plane(p);
+    if (kind == 2) { i += pex(p); j += per(p); }
+    return base + ((int64_t)p * plane + node_index(pitch, i, j));
+  }
+  __device__ __forceinline__ float load(const JetDesc &d, int p, int i, int j) const {
+    return C::dec(*at(p, i, j), pop_offset<C>(d, p), d.one);
+  }
+  __device__ __forceinline__ void put(const JetDesc &d, int p, int i, int j, float v) const {
+    *at(p, i, j) = C::enc(v, pop_offset<C>(d, p), d.one);
+  }
+  __device__ __forceinline__ float pulled(const JetDesc &d, int p, int i, int j) const {
+    const gptr<T> q = kind == 2 ? base + ((int64_t)p * plane + node_index(pitch, i, j))
+                                : at(p, i - pex(p), j - per(p));
+    return C::dec(*q, pop_offset<C>(d, p), d.one);
+  }
+};
+
+template <class C>
+__device__ __forceinline__ State<C> state_view(const JetDesc &d, int32_t view) {
+  return State<C>{as_global(static_cast<typename C::T *>(d.buf[view == 1 ? 1 : 0])), d.plane,
+                  d.pitch, view < 2 ? 0 : view - 1};
+}
+
+// The 13 values node (i, j) pulls, through a view.
+template <class C>
+__device__ __forceinline__ void pulled_node(const JetDesc &d, const State<C> &s, int i, int j,
+                                            float (&f)[9], float (&g)[4]) {
+#pragma unroll
+  for (int p = 0; p < NPOP; ++p) {
+    const float v = s.pulled(d, p, i, j);
+    if (p < 9) f[p] = v; else g[p - 9] = v;
+  }
+}
+
+// If the value node (i, j) pulls along p comes from outside the domain and
+// the edge rules (r side first, as pull_edge) resolve it to an equilibrium
+// side, set v to it and return true.
+__device__ __forceinline__ bool eq_pull(const JetDesc &d, int p, int i, int j, float &v) {
+  const int ip = i - pex(p), jp = j - per(p);
+  int pp = p;
+  if (jp < 0 || jp >= d.nr) {
+    const int side = jp < 0 ? 2 : 3;
+    const int bc = d.bc[side];
+    if (bc == BC_EQ) {
+      const float *e = d.eq[side];
+      v = eq_plane(p, e[0], e[1], e[2], e[3]);
+      return true;
+    }
+    if (bc != BC_AXIS && bc != BC_FREESLIP) return false;
+    pp = p < 9 ? mir9(p) : 9 + mir4(p - 9);  // the mirrored link, x rule
+  }
+  if (ip >= 0 && ip < d.nx) return false;
+  const int side = ip < 0 ? 0 : 1;
+  if (d.bc[side] != BC_EQ) return false;
+  const float *e = d.eq[side];
+  v = eq_plane(pp, e[0], e[1], e[2], e[3]);
+  return true;
 }
 
 // Thermal wall: anti-bounce-back towards the wall temperature, or plain
@@ -483,6 +573,26 @@ __device__ __forceinline__ void ghost_epilogue(const JetDesc &d, const O &o, int
     if (i == 0 && x1 == BC_PERIODIC) o.put(d, 7, nx, nr, f[6]);
     if (i == nx - 1 && x1 == BC_OUTFLOW) o.put(d, 7, nx, nr, f[6]);
     if (i == nx - 1 && x1 == BC_WALL) o.put(d, 7, nx, nr, f[8]);
+  }
+}
+
+// Epilogue of a single-buffer step: the producer-written ghost values, plus
+// the constant values of equilibrium sides that this edge node pulls (the
+// single buffer does not keep them between steps).  `o` is the view of the
+// state the step produces.
+template <class C>
+__device__ __forceinline__ void aa_epilogue(const JetDesc &d, const State<C> &o, int i, int j,
+                                            const float (&f)[9], const float (&g)[4],
+                                            const float4 *in) {
+  ghost_epilogue<C>(d, o, i, j, f, g, in);
+  if ((d.bc[0] == BC_EQ) | (d.bc[1] == BC_EQ) | (d.bc[2] == BC_EQ) | (d.bc[3] == BC_EQ)) {
+#pragma unroll
+    for (int p = 1; p < NPOP; ++p) {
+      const int gi = i - pex(p), gj = j - per(p);
+      float v;
+      if ((gi < 0 || gi >= d.nx || gj < 0 || gj >= d.nr) && eq_pull(d, p, i, j, v))
+        o.put(d, p, gi, gj, v);
+    }
   }
 }
 

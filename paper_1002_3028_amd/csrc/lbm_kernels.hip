@@ -48,6 +48,7 @@ int validate_config(const lbm_config *c, bool check_precision) {
          !std::isfinite(c->eq_state[s][3])))
       return LBM_EINVAL;
   if (c->hoop != 0 && c->hoop != 1) return LBM_EINVAL;
+  if (c->layout != LBM_LAYOUT_TWO_BUFFERS && c->layout != LBM_LAYOUT_SINGLE) return LBM_EINVAL;
   if (!(c->rho0 > 0.0) || !std::isfinite(c->rho0) || !std::isfinite(c->ux0) ||
       !std::isfinite(c->ur0) || !std::isfinite(c->T0))
     return LBM_EINVAL;
@@ -183,6 +184,18 @@ int launch_step(int shape, int prec, int grid, hipStream_t st, const JetDesc *je
   return LBM_OK;
 }
 
+int launch_aa_step(int prec, int grid, hipStream_t st, const JetDesc *jets, const int32_t *tiles,
+                   const BatchHdr *hdr, int32_t koff, int32_t *flags) {
+  static const void *fn[3] = {(const void *)&aa_kernel<CodecF32>,
+                              (const void *)&aa_kernel<CodecF16>,
+                              (const void *)&aa_kernel<CodecBF16>};
+  int32_t tog = 0, nsteps = 1;
+  void *args[] = {(void *)&jets, (void *)&tiles, (void *)&hdr,   (void *)&koff,
+                  (void *)&tog,  (void *)&nsteps, (void *)&flags};
+  LBM_HIP(hipLaunchKernel(fn[codec_index(prec)], dim3(grid), dim3(64, 4), args, 0, st));
+  return LBM_OK;
+}
+
 int launch_advance(hipStream_t st, JetDesc *jets, const BatchHdr *hdr, int32_t njets_max,
                    int32_t delta, int32_t npair) {
   const int blocks = (njets_max + 63) / 64;
@@ -192,76 +205,76 @@ int launch_advance(hipStream_t st, JetDesc *jets, const BatchHdr *hdr, int32_t n
 }
 
 template <class C>
-static void init_t(hipStream_t st, const JetDesc *d, const lbm_config *c, int64_t step, int32_t flip,
+static void init_t(hipStream_t st, const JetDesc *d, const lbm_config *c, int64_t step, int32_t view,
                    const float4 *state, float4 u0) {
   hipLaunchKernelGGL(init_kernel<C>, dim3((c->nx + 255) / 256, c->nr), dim3(256), 0, st, d,
-                     step, flip, state, u0);
+                     step, view, state, u0);
 }
-int launch_init(int prec, hipStream_t st, const JetDesc *d, const lbm_config *c, int64_t step, int32_t flip,
+int launch_init(int prec, hipStream_t st, const JetDesc *d, const lbm_config *c, int64_t step, int32_t view,
                 const float4 *state, float4 u0) {
-  if (prec == LBM_PREC_FP32) init_t<CodecF32>(st, d, c, step, flip, state, u0);
-  else if (prec == LBM_PREC_FP16DEV) init_t<CodecF16>(st, d, c, step, flip, state, u0);
-  else init_t<CodecBF16>(st, d, c, step, flip, state, u0);
+  if (prec == LBM_PREC_FP32) init_t<CodecF32>(st, d, c, step, view, state, u0);
+  else if (prec == LBM_PREC_FP16DEV) init_t<CodecF16>(st, d, c, step, view, state, u0);
+  else init_t<CodecBF16>(st, d, c, step, view, state, u0);
   LBM_HIP(hipGetLastError());
   return LBM_OK;
 }
 
 template <class C>
-static void ghost_t(hipStream_t st, const JetDesc *d, const lbm_config *c, int64_t step, int32_t flip) {
+static void ghost_t(hipStream_t st, const JetDesc *d, const lbm_config *c, int64_t step, int32_t view) {
   const int n = 2 * (c->nx + 2) + 2 * c->nr;
-  hipLaunchKernelGGL(ghost_fill_kernel<C>, dim3((n + 255) / 256), dim3(256), 0, st, d, step, flip);
+  hipLaunchKernelGGL(ghost_fill_kernel<C>, dim3((n + 255) / 256), dim3(256), 0, st, d, step, view);
 }
 int launch_ghost_fill(int prec, hipStream_t st, const JetDesc *d, const lbm_config *c,
-                      int64_t step, int32_t flip) {
-  if (prec == LBM_PREC_FP32) ghost_t<CodecF32>(st, d, c, step, flip);
-  else if (prec == LBM_PREC_FP16DEV) ghost_t<CodecF16>(st, d, c, step, flip);
-  else ghost_t<CodecBF16>(st, d, c, step, flip);
+                      int64_t step, int32_t view) {
+  if (prec == LBM_PREC_FP32) ghost_t<CodecF32>(st, d, c, step, view);
+  else if (prec == LBM_PREC_FP16DEV) ghost_t<CodecF16>(st, d, c, step, view);
+  else ghost_t<CodecBF16>(st, d, c, step, view);
   LBM_HIP(hipGetLastError());
   return LBM_OK;
 }
 
 template <class C>
-static void moments_t(hipStream_t st, const JetDesc *d, const lbm_config *c, int64_t step, int32_t flip,
+static void moments_t(hipStream_t st, const JetDesc *d, const lbm_config *c, int64_t step, int32_t view,
                       float4 *out) {
   hipLaunchKernelGGL(moments_kernel<C>, dim3((c->nx + 255) / 256, c->nr), dim3(256), 0, st, d,
-                     step, flip, out);
+                     step, view, out);
 }
 int launch_moments(int prec, hipStream_t st, const JetDesc *d, const lbm_config *c,
-                   int64_t step, int32_t flip, float4 *out) {
-  if (prec == LBM_PREC_FP32) moments_t<CodecF32>(st, d, c, step, flip, out);
-  else if (prec == LBM_PREC_FP16DEV) moments_t<CodecF16>(st, d, c, step, flip, out);
-  else moments_t<CodecBF16>(st, d, c, step, flip, out);
+                   int64_t step, int32_t view, float4 *out) {
+  if (prec == LBM_PREC_FP32) moments_t<CodecF32>(st, d, c, step, view, out);
+  else if (prec == LBM_PREC_FP16DEV) moments_t<CodecF16>(st, d, c, step, view, out);
+  else moments_t<CodecBF16>(st, d, c, step, view, out);
   LBM_HIP(hipGetLastError());
   return LBM_OK;
 }
 
 template <class C>
-static void profiles_t(hipStream_t st, const JetDesc *d, const lbm_config *c, int64_t step, int32_t flip,
+static void profiles_t(hipStream_t st, const JetDesc *d, const lbm_config *c, int64_t step, int32_t view,
                        float2 *out) {
   const int n = c->nx + c->nr;
-  hipLaunchKernelGGL(profiles_kernel<C>, dim3((n + 255) / 256), dim3(256), 0, st, d, step, flip, out);
+  hipLaunchKernelGGL(profiles_kernel<C>, dim3((n + 255) / 256), dim3(256), 0, st, d, step, view, out);
 }
 int launch_profiles(int prec, hipStream_t st, const JetDesc *d, const lbm_config *c,
-                    int64_t step, int32_t flip, float2 *out) {
-  if (prec == LBM_PREC_FP32) profiles_t<CodecF32>(st, d, c, step, flip, out);
-  else if (prec == LBM_PREC_FP16DEV) profiles_t<CodecF16>(st, d, c, step, flip, out);
-  else profiles_t<CodecBF16>(st, d, c, step, flip, out);
+                    int64_t step, int32_t view, float2 *out) {
+  if (prec == LBM_PREC_FP32) profiles_t<CodecF32>(st, d, c, step, view, out);
+  else if (prec == LBM_PREC_FP16DEV) profiles_t<CodecF16>(st, d, c, step, view, out);
+  else profiles_t<CodecBF16>(st, d, c, step, view, out);
   LBM_HIP(hipGetLastError());
   return LBM_OK;
 }
 
 template <class C>
-static void cons_t(hipStream_t st, const JetDesc *d, int64_t step, int32_t flip, RedPartial *partial,
+static void cons_t(hipStream_t st, const JetDesc *d, int64_t step, int32_t view, RedPartial *partial,
                    int nblocks) {
-  hipLaunchKernelGGL(conservation_kernel<C>, dim3(nblocks), dim3(RED_THREADS), 0, st, d, step, flip,
+  hipLaunchKernelGGL(conservation_kernel<C>, dim3(nblocks), dim3(RED_THREADS), 0, st, d, step, view,
                      partial);
 }
-int launch_conservation(int prec, hipStream_t st, const JetDesc *d, int64_t nodes, int64_t step, int32_t flip,
+int launch_conservation(int prec, hipStream_t st, const JetDesc *d, int64_t nodes, int64_t step, int32_t view,
                         RedPartial *partial, int nblocks, RedPartial *out) {
   (void)nodes;
-  if (prec == LBM_PREC_FP32) cons_t<CodecF32>(st, d, step, flip, partial, nblocks);
-  else if (prec == LBM_PREC_FP16DEV) cons_t<CodecF16>(st, d, step, flip, partial, nblocks);
-  else cons_t<CodecBF16>(st, d, step, flip, partial, nblocks);
+  if (prec == LBM_PREC_FP32) cons_t<CodecF32>(st, d, step, view, partial, nblocks);
+  else if (prec == LBM_PREC_FP16DEV) cons_t<CodecF16>(st, d, step, view, partial, nblocks);
+  else cons_t<CodecBF16>(st, d, step, view, partial, nblocks);
   LBM_HIP(hipGetLastError());
   hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(RED_THREADS), 0, st, partial, nblocks,
                      out);
@@ -270,31 +283,31 @@ int launch_conservation(int prec, hipStream_t st, const JetDesc *d, int64_t node
 }
 
 template <class C>
-static void decode_t(hipStream_t st, const JetDesc *d, const lbm_config *c, int64_t step, int32_t flip,
+static void decode_t(hipStream_t st, const JetDesc *d, const lbm_config *c, int64_t step, int32_t view,
                      float *out) {
   hipLaunchKernelGGL(decode_kernel<C>, dim3((c->nx + 255) / 256, c->nr, NPOP), dim3(256), 0, st,
-                     d, step, flip, out);
+                     d, step, view, out);
 }
-int launch_decode(int prec, hipStream_t st, const JetDesc *d, const lbm_config *c, int64_t step, int32_t flip,
+int launch_decode(int prec, hipStream_t st, const JetDesc *d, const lbm_config *c, int64_t step, int32_t view,
                   float *out) {
-  if (prec == LBM_PREC_FP32) decode_t<CodecF32>(st, d, c, step, flip, out);
-  else if (prec == LBM_PREC_FP16DEV) decode_t<CodecF16>(st, d, c, step, flip, out);
-  else decode_t<CodecBF16>(st, d, c, step, flip, out);
+  if (prec == LBM_PREC_FP32) decode_t<CodecF32>(st, d, c, step, view, out);
+  else if (prec == LBM_PREC_FP16DEV) decode_t<CodecF16>(st, d, c, step, view, out);
+  else decode_t<CodecBF16>(st, d, c, step, view, out);
   LBM_HIP(hipGetLastError());
   return LBM_OK;
 }
 
 template <class C>
-static void encode_t(hipStream_t st, const JetDesc *d, const lbm_config *c, int64_t step, int32_t flip,
+static void encode_t(hipStream_t st, const JetDesc *d, const lbm_config *c, int64_t step, int32_t view,
                      const float *in) {
   hipLaunchKernelGGL(encode_kernel<C>, dim3((c->nx + 255) / 256, c->nr, NPOP), dim3(256), 0, st,
-                     d, step, flip, in);
+                     d, step, view, in);
 }
-int launch_encode(int prec, hipStream_t st, const JetDesc *d, const lbm_config *c, int64_t step, int32_t flip,
+int launch_encode(int prec, hipStream_t st, const JetDesc *d, const lbm_config *c, int64_t step, int32_t view,
                   const float *in) {
-  if (prec == LBM_PREC_FP32) encode_t<CodecF32>(st, d, c, step, flip, in);
-  else if (prec == LBM_PREC_FP16DEV) encode_t<CodecF16>(st, d, c, step, flip, in);
-  else encode_t<CodecBF16>(st, d, c, step, flip, in);
+  if (prec == LBM_PREC_FP32) encode_t<CodecF32>(st, d, c, step, view, in);
+  else if (prec == LBM_PREC_FP16DEV) encode_t<CodecF16>(st, d, c, step, view, in);
+  else encode_t<CodecBF16>(st, d, c, step, view, in);
   LBM_HIP(hipGetLastError());
   return LBM_OK;
 }

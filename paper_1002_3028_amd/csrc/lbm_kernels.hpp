@@ -445,14 +445,101 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(W, 8)))
   }
 }
 
-// Ghost ring of buf[(step + flip) & 1] from its interior and the inlet row of `step`,
-// by the pull-side edge rules: every ghost slot (ghost node, link p) whose
-// puller (ghost + e_p) is a fluid node gets the value that node pulls.  Run
-// after any change of the interior or of the inlet made outside the step.
+// ---------------------------------------------------------------------------
+// Single-buffer (AA) step over the same 64 x 4 tiles as the one-step kernel's
+// default shape, one node per lane.  After an even number of steps the buffer
+// is in the swapped layout: a node pulls from its neighbours (plane opp(p) at
+// x - e_p), collides and pushes f*_p into plane p at x + e_p, leaving the
+// natural layout.  After an odd number it reads its own 13 values, collides
+// and writes f*_p into plane opp(p) of its own node, leaving the swapped
+// layout.  Edge nodes then write what the next step pulls from outside the
+// domain.  Each location is read and written by a single thread in a step,
+// so the update is in place; the per-node arithmetic is the one-step
+// kernel's, so the results are bit-identical to the two-buffer scheme.
+// ---------------------------------------------------------------------------
+template <class C>
+__global__ __launch_bounds__(256) void aa_kernel(
+    const JetDesc *__restrict__ jets, const int32_t *__restrict__ tile_start,
+    const BatchHdr *__restrict__ hdr, int32_t koff, int32_t tog, int32_t nsteps,
+    int32_t *__restrict__ flags) {
+  using T = typename C::T;
+  constexpr int ES = (int)sizeof(T);
+  const int lane = (int)threadIdx.x, wave = (int)threadIdx.y;
+  const int32_t njets = hdr->njets;
+  const int32_t ntiles = tile_start[njets];
+  const int32_t G = gridDim.x;  // a multiple of 8
+  const int32_t per_xcd = G >> 3;
+  const int32_t b = blockIdx.x;
+  for (int32_t t = (b & 7) * per_xcd + (b >> 3); t < ntiles; t += G) {
+    int32_t jid = 0;
+    if (njets > 1) {  // last jet whose first tile is <= t
+      int32_t lo = 0, hi = njets - 1;
+      while (lo < hi) {
+        const int32_t mid = (lo + hi + 1) >> 1;
+        if (tile_start[mid] <= t) lo = mid; else hi = mid - 1;
+      }
+      jid = lo;
+    }
+    const JetDesc &d = jets[jid];
+    const int64_t step = d.step0 + koff;
+    if (step >= d.target) continue;
+    const int32_t lt = t - tile_start[jid];
+    const int32_t ty = lt / d.tiles_x;
+    const int32_t tx = lt - ty * d.tiles_x;
+    const int i = tx * 64 + lane, j = ty * 4 + wave;
+    if ((i < d.nx) & (j < d.nr)) {
+      T *raw = static_cast<T *>(d.buf[0]);
+      const uint32_t pitch_b = (uint32_t)d.pitch * ES, plane_b = (uint32_t)d.plane * ES;
+      const __amdgpu_buffer_rsrc_t r =
+          __builtin_amdgcn_make_buffer_rsrc(raw, 0, (int)((uint32_t)NPOP * plane_b), BUF_WORD3);
+      const uint32_t voff = (uint32_t)node_index(d.pitch, i, j) * ES;
+      const bool swapped = (step & 1) == 0;
+      typename Raw<ES>::type w[NPOP];
+      if (swapped) {
+#pragma unroll
+        for (int p = 0; p < NPOP; ++p)
+          w[p] = buf_load<ES, 0>(r, voff,
+                                 (uint32_t)opp_plane(p) * plane_b -
+                                     (uint32_t)(per(p) * (int)pitch_b) -
+                                     (uint32_t)(pex(p) * ES));
+      } else {
+#pragma unroll
+        for (int p = 0; p < NPOP; ++p) w[p] = buf_load<ES, 0>(r, voff, (uint32_t)p * plane_b);
+      }
+      float f[9], g[4];
+      decode_raw<C>(d, w, f, g);
+      const float rr = d.r0 + (float)j + 0.5f;
+      const bool ok = collide(d, fast_rcp(rr), rr * rr, f, g);
+#pragma unroll
+      for (int p = 0; p < NPOP; ++p) {
+        const T x = C::enc(p < 9 ? f[p] : g[p - 9], pop_offset<C>(d, p), d.one);
+        const uint32_t soff =
+            swapped ? (uint32_t)p * plane_b + (uint32_t)(per(p) * (int)pitch_b) +
+                          (uint32_t)(pex(p) * ES)
+                    : (uint32_t)opp_plane(p) * plane_b;
+        buf_store<ES, 0>(__builtin_bit_cast(typename Raw<ES>::type, x), r, voff, soff);
+      }
+      if (is_edge(d, i, j)) {
+        const float4 *in1 = d.bc[0] == BC_INLET
+                                ? d.inlet + (int64_t)((step + 1) % d.n_t) * d.nr
+                                : d.inlet;
+        const State<C> o{as_global(raw), d.plane, d.pitch, swapped ? 2 : 1};
+        aa_epilogue<C>(d, o, i, j, f, g, in1);
+      }
+      if (!ok) flags[d.slot] = 1;
+    }
+  }
+}
+
+// Ghost values of the state after `step` steps (seen through `view`) from its
+// interior and the inlet row of `step`, by the pull-side edge rules: every
+// ghost slot (ghost node, link p) whose puller (ghost + e_p) is a fluid node
+// gets the value that node pulls.  Run after any change of the interior or
+// of the inlet made outside the step.
 // One thread per ghost node: row -1 and row nr (nx + 2 each, corners
 // included), then columns -1 and nx (nr each).
 template <class C>
-__global__ void ghost_fill_kernel(const JetDesc *__restrict__ dp, int64_t step, int32_t flip) {
+__global__ void ghost_fill_kernel(const JetDesc *__restrict__ dp, int64_t step, int32_t view) {
   const JetDesc &d = *dp;
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   const int nx = d.nx, nr = d.nr;
@@ -462,16 +549,13 @@ __global__ void ghost_fill_kernel(const JetDesc *__restrict__ dp, int64_t step, 
   else if (q < 2 * (nx + 2) + nr) { gi = -1; gj = q - 2 * (nx + 2); }
   else if (q < 2 * (nx + 2) + 2 * nr) { gi = nx; gj = q - 2 * (nx + 2) - nr; }
   else return;
-  using T = typename C::T;
-  T *raw = static_cast<T *>(d.buf[(step + flip) & 1]);
-  const Src<C> s{as_global(static_cast<const T *>(raw)), d.plane, d.pitch};
-  const Dst<C> o{as_global(raw), d.plane, d.pitch};
+  const State<C> st = state_view<C>(d, view);
   const float4 *inrow = d.inlet + (int64_t)(step % d.n_t) * d.nr;
 #pragma unroll
   for (int p = 1; p < NPOP; ++p) {
     const int pi = gi + pex(p), pj = gj + per(p);
     if (pi >= 0 && pi < nx && pj >= 0 && pj < nr)
-      o.put(d, p, gi, gj, pull_edge<C>(d, s, p, pi, pj, inrow));
+      st.put(d, p, gi, gj, pull_edge<C>(d, st, p, pi, pj, inrow));
   }
 }
 
@@ -493,32 +577,31 @@ __global__ void advance_kernel(JetDesc *__restrict__ jets, const BatchHdr *__res
   }
 }
 
-// Equilibrium fill of buf[(step + flip) & 1] from fields (float4 rho, ux, ur, T per
-// node, i fastest) or, with state == nullptr, from the uniform u0.
+// Equilibrium fill of the state (through `view`) from fields (float4 rho, ux,
+// ur, T per node, i fastest) or, with state == nullptr, from the uniform u0.
 template <class C>
-__global__ void init_kernel(const JetDesc *__restrict__ dp, int64_t step, int32_t flip,
+__global__ void init_kernel(const JetDesc *__restrict__ dp, int64_t step, int32_t view,
                             const float4 *__restrict__ state, float4 u0) {
   const JetDesc &d = *dp;
   const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
   if (i >= d.nx) return;
   const float4 q = state ? state[(int64_t)j * d.nx + i] : u0;
-  typename C::T *o = static_cast<typename C::T *>(d.buf[(step + flip) & 1]) + node_index(d.pitch, i, j);
+  const State<C> st = state_view<C>(d, view);
 #pragma unroll
-  for (int p = 0; p < NPOP; ++p)
-    o[(int64_t)p * d.plane] = C::enc(eq_plane(p, q.x, q.y, q.z, q.w), pop_offset<C>(d, p), d.one);
+  for (int p = 0; p < NPOP; ++p) st.put(d, p, i, j, eq_plane(p, q.x, q.y, q.z, q.w));
 }
 
 // Pre-collision moments (eq. 2) of the state after `step` steps:
 // float4 (rho, ux, ur, T) per node, i fastest.
 template <class C>
-__global__ void moments_kernel(const JetDesc *__restrict__ dp, int64_t step, int32_t flip,
+__global__ void moments_kernel(const JetDesc *__restrict__ dp, int64_t step, int32_t view,
                                float4 *__restrict__ out) {
   const JetDesc &d = *dp;
   const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y;
   if (i >= d.nx) return;
-  Src<C> s{as_global(static_cast<const typename C::T *>(d.buf[(step + flip) & 1])), d.plane, d.pitch};
+  const State<C> s = state_view<C>(d, view);
   float f[9], g[4];
-  pull_node<C>(d, s, i, j, f, g);
+  pulled_node<C>(d, s, i, j, f, g);
   const float rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
   const float mx = (f[1] + f[5] + f[8]) - (f[3] + f[6] + f[7]);
   const float mr = (f[2] + f[5] + f[6]) - (f[4] + f[7] + f[8]);
@@ -528,16 +611,16 @@ __global__ void moments_kernel(const JetDesc *__restrict__ dp, int64_t step, int
 
 // Centreline (j = 0) and exit column (i = nx-1): (ux, T) pairs, nx + nr.
 template <class C>
-__global__ void profiles_kernel(const JetDesc *__restrict__ dp, int64_t step, int32_t flip,
+__global__ void profiles_kernel(const JetDesc *__restrict__ dp, int64_t step, int32_t view,
                                 float2 *__restrict__ out) {
   const JetDesc &d = *dp;
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= d.nx + d.nr) return;
   const int i = t < d.nx ? t : d.nx - 1;
   const int j = t < d.nx ? 0 : t - d.nx;
-  Src<C> s{as_global(static_cast<const typename C::T *>(d.buf[(step + flip) & 1])), d.plane, d.pitch};
+  const State<C> s = state_view<C>(d, view);
   float f[9], g[4];
-  pull_node<C>(d, s, i, j, f, g);
+  pulled_node<C>(d, s, i, j, f, g);
   const float rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
   const float mx = (f[1] + f[5] + f[8]) - (f[3] + f[6] + f[7]);
   out[t] = make_float2(mx / rho, (g[0] + g[1]) + (g[2] + g[3]));
@@ -551,16 +634,16 @@ __global__ void profiles_kernel(const JetDesc *__restrict__ dp, int64_t step, in
 // non-finite rho or T.
 template <class C>
 __global__ __launch_bounds__(RED_THREADS) void conservation_kernel(
-    const JetDesc *__restrict__ dp, int64_t step, int32_t flip, RedPartial *__restrict__ partial) {
+    const JetDesc *__restrict__ dp, int64_t step, int32_t view, RedPartial *__restrict__ partial) {
   const JetDesc &d = *dp;
-  Src<C> s{as_global(static_cast<const typename C::T *>(d.buf[(step + flip) & 1])), d.plane, d.pitch};
+  const State<C> s = state_view<C>(d, view);
   const int64_t nodes = (int64_t)d.nx * d.nr;
   double m = 0.0, e = 0.0, bad = 0.0;
   for (int64_t n = (int64_t)blockIdx.x * RED_THREADS + threadIdx.x; n < nodes;
        n += (int64_t)gridDim.x * RED_THREADS) {
     const int j = (int)(n / d.nx), i = (int)(n - (int64_t)j * d.nx);
     float f[9], g[4];
-    pull_node<C>(d, s, i, j, f, g);
+    pulled_node<C>(d, s, i, j, f, g);
     const float rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
     const float T = (g[0] + g[1]) + (g[2] + g[3]);
     const double r = (double)d.r0 + (double)j + 0.5;
@@ -610,25 +693,21 @@ __global__ __launch_bounds__(RED_THREADS) void reduce_partials_kernel(
 
 // Stored populations <-> dense FP32 planes (13 x nr x nx, no pitch).
 template <class C>
-__global__ void decode_kernel(const JetDesc *__restrict__ dp, int64_t step, int32_t flip,
+__global__ void decode_kernel(const JetDesc *__restrict__ dp, int64_t step, int32_t view,
                               float *__restrict__ out) {
   const JetDesc &d = *dp;
   const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y, p = blockIdx.z;
   if (i >= d.nx) return;
-  const typename C::T *b = static_cast<const typename C::T *>(d.buf[(step + flip) & 1]);
-  out[((int64_t)p * d.nr + j) * d.nx + i] =
-      C::dec(b[(int64_t)p * d.plane + node_index(d.pitch, i, j)], pop_offset<C>(d, p), d.one);
+  out[((int64_t)p * d.nr + j) * d.nx + i] = state_view<C>(d, view).load(d, p, i, j);
 }
 
 template <class C>
-__global__ void encode_kernel(const JetDesc *__restrict__ dp, int64_t step, int32_t flip,
+__global__ void encode_kernel(const JetDesc *__restrict__ dp, int64_t step, int32_t view,
                               const float *__restrict__ in) {
   const JetDesc &d = *dp;
   const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y, p = blockIdx.z;
   if (i >= d.nx) return;
-  typename C::T *b = static_cast<typename C::T *>(d.buf[(step + flip) & 1]);
-  b[(int64_t)p * d.plane + node_index(d.pitch, i, j)] =
-      C::enc(in[((int64_t)p * d.nr + j) * d.nx + i], pop_offset<C>(d, p), d.one);
+  state_view<C>(d, view).put(d, p, i, j, in[((int64_t)p * d.nr + j) * d.nx + i]);
 }
 
 // Plain streaming copy, 16 B per lane per iteration.

@@ -29,6 +29,15 @@ inline size_t buffer_bytes(const lbm_config *c, int prec) {
   return align256((size_t)NPOP * (size_t)layout_plane(c->nx, c->nr) * storage_bytes(prec));
 }
 
+// Buffers per jet: two, or one in place.
+inline int n_buffers(int layout) { return layout == LBM_LAYOUT_SINGLE ? 1 : 2; }
+
+// The view (see State in lbm_device.hpp) of the state after `step` steps.
+inline int32_t state_view_of(int layout, int64_t step, int32_t flip) {
+  if (layout == LBM_LAYOUT_SINGLE) return 2 + (int32_t)(step & 1);
+  return (int32_t)((step + flip) & 1);
+}
+
 int validate_config(const lbm_config *c, bool check_precision);
 
 // Host copy of the property tables as (M, dM) pairs at each grid point.
@@ -68,21 +77,25 @@ int launch_step(int shape, int prec, int grid, hipStream_t st, const JetDesc *je
 // two-step launches.
 int launch_advance(hipStream_t st, JetDesc *jets, const BatchHdr *hdr, int32_t njets_max,
                    int32_t delta, int32_t npair);
-// Helpers on the state after `step` steps, held in buf[(step + flip) & 1].
+// Single-buffer step over shape 0's tile list.
+int launch_aa_step(int prec, int grid, hipStream_t st, const JetDesc *jets, const int32_t *tiles,
+                   const BatchHdr *hdr, int32_t koff, int32_t *flags);
+// Helpers on the state after `step` steps, seen through `view`
+// (state_view_of).
 int launch_init(int prec, hipStream_t st, const JetDesc *d, const lbm_config *c, int64_t step,
-                int32_t flip, const float4 *state, float4 u0);
+                int32_t view, const float4 *state, float4 u0);
 int launch_ghost_fill(int prec, hipStream_t st, const JetDesc *d, const lbm_config *c,
-                      int64_t step, int32_t flip);
+                      int64_t step, int32_t view);
 int launch_moments(int prec, hipStream_t st, const JetDesc *d, const lbm_config *c,
-                   int64_t step, int32_t flip, float4 *out);
+                   int64_t step, int32_t view, float4 *out);
 int launch_profiles(int prec, hipStream_t st, const JetDesc *d, const lbm_config *c,
-                    int64_t step, int32_t flip, float2 *out);
+                    int64_t step, int32_t view, float2 *out);
 int launch_conservation(int prec, hipStream_t st, const JetDesc *d, int64_t nodes, int64_t step,
-                        int32_t flip, RedPartial *partial, int nblocks, RedPartial *out);
+                        int32_t view, RedPartial *partial, int nblocks, RedPartial *out);
 int launch_decode(int prec, hipStream_t st, const JetDesc *d, const lbm_config *c, int64_t step,
-                  int32_t flip, float *out);
+                  int32_t view, float *out);
 int launch_encode(int prec, hipStream_t st, const JetDesc *d, const lbm_config *c, int64_t step,
-                  int32_t flip, const float *in);
+                  int32_t view, const float *in);
 
 int tiles_of(const lbm_config *c, int shape, int32_t *tiles_x);
 

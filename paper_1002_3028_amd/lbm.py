@@ -16,10 +16,11 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbm_hip.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 OK, EINVAL, ENOMEM, EUNSTABLE, EDEVICE, ESTATE = 0, -1, -2, -3, -4, -5
 PRECISION = {"fp32": 1, "fp16": 2, "bf16": 3}
 BC = {"inlet": 0, "outflow": 1, "periodic": 2, "axis": 3, "freeslip": 4, "wall": 5, "eq": 6}
+LAYOUT = {"two": 0, "single": 1}  # two buffers, or one updated in place
 
 
 class LbmError(RuntimeError):
@@ -48,6 +49,7 @@ class _Config(ctypes.Structure):
         ("hoop", ctypes.c_int32),
         ("precision", ctypes.c_int32),
         ("rho_ref", ctypes.c_double), ("g_ref", ctypes.c_double),
+        ("layout", ctypes.c_int32),
     ]
 
 
@@ -92,6 +94,7 @@ _SIGS = {
                          ctypes.c_int),
     "lbm_batch_set_launch": ([_vp, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
     "lbm_batch_set_cohort_bytes": ([_vp, ctypes.c_size_t], ctypes.c_int),
+    "lbm_batch_set_layout": ([_vp, ctypes.c_int32], ctypes.c_int),
     "lbm_batch_destroy": ([_vp], None),
     "lbm_tile_shape_count": ([], ctypes.c_int),
     "lbm_tile_shape": ([ctypes.c_int32] + [ctypes.POINTER(ctypes.c_int32)] * 4, ctypes.c_int),
@@ -142,7 +145,8 @@ def _ptr(a):
     return a.ctypes.data_as(_dp) if a is not None else None
 
 
-def make_config(p: dict, precision: str = "fp32", rho_ref: float = 1.0, g_ref: float = 0.0):
+def make_config(p: dict, precision: str = "fp32", rho_ref: float = 1.0, g_ref: float = 0.0,
+                layout: str = "two"):
     """Parameter dict -> lbm_config (plus arrays that must stay alive)."""
     c = _Config()
     c.abi_version = ABI_VERSION
@@ -180,11 +184,12 @@ def make_config(p: dict, precision: str = "fp32", rho_ref: float = 1.0, g_ref: f
     c.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
     c.rho_ref = float(rho_ref)
     c.g_ref = float(g_ref)
+    c.layout = LAYOUT[layout] if isinstance(layout, str) else int(layout)
     return c, keep
 
 
-def bytes_required(p: dict, precision="fp32") -> int:
-    cfg, keep = make_config(p, precision)
+def bytes_required(p: dict, precision="fp32", layout="two") -> int:
+    cfg, keep = make_config(p, precision, layout=layout)
     n = ctypes.c_size_t()
     _check(load().lbm_bytes_required(ctypes.byref(cfg), ctypes.byref(n)), "lbm_bytes_required")
     return int(n.value)
@@ -218,18 +223,20 @@ class Solver:
     """One jet on the current HIP device.
 
     Population buffers come from a torch uint8 tensor and work runs on a torch
-    stream (default priority) unless ``stream`` is given.
+    stream (default priority) unless ``stream`` is given.  layout="single"
+    keeps one buffer updated in place (half the memory, same results).
     """
 
     def __init__(self, params: dict, precision: str = "fp32", rho_ref: float = 1.0,
-                 g_ref: float = 0.0, stream=None, graph_steps: int = 0, tile_shape=None):
+                 g_ref: float = 0.0, stream=None, graph_steps: int = 0, tile_shape=None,
+                 layout: str = "two"):
         import torch
 
         lib = load()
         self.lib = lib
         self.nx, self.nr = int(params["nx"]), int(params["nr"])
         self.precision = precision
-        cfg, keep = make_config(params, precision, rho_ref, g_ref)
+        cfg, keep = make_config(params, precision, rho_ref, g_ref, layout)
         n = ctypes.c_size_t()
         _check(lib.lbm_bytes_required(ctypes.byref(cfg), ctypes.byref(n)), "lbm_bytes_required")
         self.mem = torch.empty(int(n.value), dtype=torch.uint8, device="cuda")
@@ -334,7 +341,8 @@ class Solver:
 class Batch:
     """Many resident jets advanced by one persistent launch per step."""
 
-    def __init__(self, budget_bytes: int, max_slots: int, precision: str = "fp32", stream=None):
+    def __init__(self, budget_bytes: int, max_slots: int, precision: str = "fp32", stream=None,
+                 layout: str = "two"):
         import torch
 
         lib = load()
@@ -347,6 +355,8 @@ class Batch:
                "lbm_batch_create")
         self.b = b
         self.shapes = {}
+        if layout != "two":
+            _check(lib.lbm_batch_set_layout(self.b, LAYOUT[layout]), "lbm_batch_set_layout")
 
     def close(self):
         if getattr(self, "b", None):

@@ -34,8 +34,11 @@ def percentile(xs, q):
 
 def serve(requests, precision: str = "fp16", budget_bytes: int = 16 << 30,
           max_slots: int = 256, k_steps: int = 50, realtime: bool = True,
-          tile_shape: int = -1, workgroups: int = 0, keep_profiles: bool = False):
+          tile_shape: int = -1, workgroups: int = 0, keep_profiles: bool = False,
+          layout: str = "two"):
     """Run the request list [(arrival_s, params, inlet, steps), ...].
+    layout="single" keeps each resident jet in one buffer updated in place,
+    so a budget holds twice as many jets.
 
     realtime=False admits every request at t = 0 (saturation: measures the
     capacity).  Returns a summary dict, plus per-request records.
@@ -48,7 +51,7 @@ def serve(requests, precision: str = "fp16", budget_bytes: int = 16 << 30,
     groups = 0
     peak_slots = 0
     peak_bytes = 0
-    with lbm.Batch(budget_bytes, max_slots, precision) as b:
+    with lbm.Batch(budget_bytes, max_slots, precision, layout=layout) as b:
         b.set_launch(tile_shape, workgroups)
         t0 = time.perf_counter()
 
@@ -116,16 +119,18 @@ def main():
     ap.add_argument("--slots", type=int, default=256)
     ap.add_argument("--k", type=int, default=50)
     ap.add_argument("--seed", type=int, default=3)
+    ap.add_argument("--layout", choices=["two", "single"], default="two")
     args = ap.parse_args()
     budget = int(args.budget_gb * (1 << 30))
     rate = args.rate
     if rate <= 0:
         cap, _ = serve(inputs.arrival_trace(args.requests, args.seed, rate=1.0), args.precision,
-                       budget, args.slots, args.k, realtime=False)
+                       budget, args.slots, args.k, realtime=False, layout=args.layout)
         print(json.dumps({"saturated": cap}), flush=True)
         rate = 0.7 * cap["requests_per_s"]
     trace = inputs.arrival_trace(args.requests, args.seed, rate=rate)
-    summary, _ = serve(trace, args.precision, budget, args.slots, args.k, realtime=True)
+    summary, _ = serve(trace, args.precision, budget, args.slots, args.k, realtime=True,
+                       layout=args.layout)
     summary["rate"] = rate
     print(json.dumps({"poisson": summary}), flush=True)
 

@@ -96,3 +96,21 @@ def test_null_safety(lib):
     lib.lbm_batch_destroy(None)
     assert lib.lbm_step_count(None) == -1
     assert lib.lbm_step(None, 1) == -1
+
+
+def test_layout_validated_and_single_buffer_is_half(lib):
+    """One buffer updated in place takes exactly half the bytes of two;
+    an unknown layout or an older config version is rejected."""
+    from paper_1002_3028_amd import lbm
+    for prec in ("fp32", "fp16"):
+        n2 = lbm.bytes_required(_params(), prec, layout="two")
+        n1 = lbm.bytes_required(_params(), prec, layout="single")
+        assert n2 == 2 * n1
+    for bad in (2, -1):
+        cfg, keep = lbm.make_config(_params(), layout=bad)
+        n = ctypes.c_size_t()
+        assert lib.lbm_bytes_required(ctypes.byref(cfg), ctypes.byref(n)) == lbm.EINVAL
+    cfg, keep = lbm.make_config(_params())
+    cfg.abi_version = 1
+    n = ctypes.c_size_t()
+    assert lib.lbm_bytes_required(ctypes.byref(cfg), ctypes.byref(n)) == lbm.EINVAL
