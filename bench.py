@@ -58,13 +58,14 @@ def read_traffic(name):
 
 
 def time_jet(params, inlet, precision, steps, warmup, graph_steps=50, check_every=1000,
-             tile_shape=None):
+             tile_shape=None, layout="two"):
     """Returns (seconds for `steps` steps, ms per step from HIP events on the
     solver's stream, 3-D mass from the FP64 check)."""
     import torch
     from paper_1002_3028_amd import lbm
 
-    with lbm.Solver(params, precision, graph_steps=graph_steps, tile_shape=tile_shape) as s:
+    with lbm.Solver(params, precision, graph_steps=graph_steps, tile_shape=tile_shape,
+                    layout=layout) as s:
         s.set_inlet(*inlet)
         s.step(warmup)
         s.sync()
@@ -246,6 +247,15 @@ def main():
             q = autotune.best_shape(pl, inl, prec)
             w, ms, _ = time_jet(pl, inl, prec, steps_l, 100, tile_shape=q)
             extra[f"{prec}_4096x1024"] = entry(prec, q, w, ms, nodes_l, steps_l)
+        # one buffer updated in place (half the memory, one step per launch)
+        for tag, (pp, ii, nn, ss) in (("2048x512", (p, inlet, nodes, steps_x)),
+                                      ("4096x1024", (pl, inl, nodes_l, steps_l))):
+            w, ms, _ = time_jet(pp, ii, "fp32", ss, 100, layout="single")
+            extra[f"fp32_{tag}_single_buffer"] = {
+                "glups": round(nn * ss / w / 1e9, 3),
+                "bytes": lbm.bytes_required(pp, "fp32", "single"),
+                "two_buffer_bytes": lbm.bytes_required(pp, "fp32", "two"),
+                "hbm_frac": round(BYTES_PER_NODE["fp32"] * nn / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         extra["batch_64_jets"] = bench_batch()
         extra["serving_fp16"] = bench_serving(precision="fp16")
         extra["serving_fp32"] = bench_serving(precision="fp32")
