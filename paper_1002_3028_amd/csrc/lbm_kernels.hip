@@ -132,7 +132,7 @@ int make_inlet(const lbm_config *c, int32_t n_t, const double *ux, const double 
     (const void *)&step_kernel<CodecBF16, BX, BY, NY, NX, W, CP>}}
 // two steps per launch: 64 x TY tiles, block 64 x NW
 #define LBM_PAIR(TY, NW, W, CP)                                                  \
-  {64, NW, (TY) / (NW), 1, W, CP, 2, NPOP * ((TY) + 2) * PAIR_W * 4,             \
+  {64, NW, (TY) / (NW), 1, W, CP, 2, (NPOP - ((CP) & 8 ? 1 : 0)) * ((TY) + 2) * PAIR_W * 4, \
    {(const void *)&pair_kernel<CodecF32, TY, NW, W, CP>,                         \
     (const void *)&pair_kernel<CodecF16, TY, NW, W, CP>,                         \
     (const void *)&pair_kernel<CodecBF16, TY, NW, W, CP>}}
@@ -146,6 +146,8 @@ static const TileShape kShapes[] = {
     LBM_PAIR(8, 4, 4, 0),          LBM_PAIR(12, 4, 3, 0),         LBM_PAIR(16, 4, 2, 0),
     LBM_PAIR(8, 4, 4, 1),          LBM_PAIR(12, 4, 3, 1),         LBM_PAIR(8, 4, 4, 4),
     LBM_PAIR(12, 4, 3, 4),         LBM_PAIR(8, 4, 4, 5),          LBM_PAIR(16, 4, 2, 4),
+    LBM_PAIR(8, 4, 5, 8),          LBM_PAIR(8, 4, 5, 9),          LBM_PAIR(8, 4, 5, 12),
+    LBM_PAIR(12, 4, 3, 8),
 };
 #undef LBM_SHAPE
 #undef LBM_PAIR
@@ -154,15 +156,16 @@ const TileShape *tile_shapes(int *count) {
   *count = (int)(sizeof(kShapes) / sizeof(kShapes[0]));
   return kShapes;
 }
-// FP32 storage: the two-step kernel on 64 x 8 tiles (the HBM traffic per
-// step halves and the arithmetic still fits under it); 16-bit storage, whose
-// step is arithmetic-limited already, and periodic jets: one step per launch.
+// FP32 storage: the two-step kernel on 64 x 8 tiles with f_0 kept in
+// registers (12-plane image, 5 workgroups per CU): the HBM traffic per step
+// halves and the arithmetic still fits under it.  16-bit storage, whose step
+// is arithmetic-limited already, and periodic jets: one step per launch.
 int default_tile_shape(int prec, bool periodic) {
   if (prec != LBM_PREC_FP32 || periodic) return 0;
   int n;
   const TileShape *s = tile_shapes(&n);
   for (int q = 0; q < n; ++q)
-    if (s[q].steps == 2 && s[q].by == 4 && s[q].by * s[q].ny == 8 && s[q].cache == 0) return q;
+    if (s[q].steps == 2 && s[q].by == 4 && s[q].by * s[q].ny == 8 && s[q].cache == 8) return q;
   return 0;
 }
 

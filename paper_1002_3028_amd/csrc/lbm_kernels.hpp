@@ -244,13 +244,20 @@ __device__ __forceinline__ bool is_edge(const JetDesc &d, int i, int j) {
 // the image are dropped.
 constexpr int PAIR_W = 66;
 
-template <class C, int EH>
+// Planes below P0 are not kept (P0 = 1: the rest population stays in the
+// registers of the thread that computed it, see pair_kernel).
+template <class C>
+__device__ __forceinline__ float storage_round(const JetDesc &d, int p, float v) {
+  const float off = pop_offset<C>(d, p);
+  return C::dec(C::enc(v, off, d.one), off, d.one);
+}
+
+template <class C, int EH, int P0>
 struct LdsImage {
   float *s;
   int ia, ja;
   __device__ __forceinline__ void set(const JetDesc &d, int p, int x, int y, float v) const {
-    const float off = pop_offset<C>(d, p);
-    s[(p * EH + y) * PAIR_W + x] = C::dec(C::enc(v, off, d.one), off, d.one);
+    if (p >= P0) s[((p - P0) * EH + y) * PAIR_W + x] = storage_round<C>(d, p, v);
   }
   __device__ __forceinline__ void put(const JetDesc &d, int p, int i, int j, float v) const {
     const int x = i - ia + 1, y = j - ja + 1;
@@ -290,8 +297,12 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(W, 8)))
   constexpr int EH = TY + 2;
   constexpr int AUX_L = (CP & 2) ? CACHE_NT : 0, AUX_S = (CP & 1) ? CACHE_NT : 0;
   constexpr bool PF = !(CP & 4);  // bit 2: no prefetch of the next task's loads
+  // bit 3: the rest population f_0 of the tile's nodes stays in registers (the
+  // wave that computes image row y in step 1 updates tile row y - 1 in step
+  // 2), so the image holds 12 planes
+  constexpr int P0 = (CP & 8) ? 1 : 0;
   static_assert(TY % NW == 0 && 2 * EH <= 64, "tile rows");
-  __shared__ float img[NPOP * EH * PAIR_W];
+  __shared__ float img[(NPOP - P0) * EH * PAIR_W];
   const int lane = (int)threadIdx.x, wave = (int)threadIdx.y;
   const int32_t njets = hdr->njets;
   const int32_t ntiles = tile_start[njets];
@@ -344,7 +355,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(W, 8)))
         }
       }
     } else {
-      const LdsImage<C, EH> im{img, ia, ja};
+      const LdsImage<C, EH, P0> im{img, ia, ja};
       // Constant ghosts (equilibrium sides) are never rewritten by the
       // epilogue: copy the ring positions of the image from the source
       // buffer first.  Every other ghost value the tile pulls is produced in
@@ -361,9 +372,9 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(W, 8)))
           if (ring) {
             float v[NPOP];
 #pragma unroll
-            for (int p = 0; p < NPOP; ++p) v[p] = src.load(d, p, i, j);
+            for (int p = P0; p < NPOP; ++p) v[p] = src.load(d, p, i, j);
 #pragma unroll
-            for (int p = 0; p < NPOP; ++p) img[(p * EH + y) * PAIR_W + x] = v[p];
+            for (int p = P0; p < NPOP; ++p) img[((p - P0) * EH + y) * PAIR_W + x] = v[p];
           }
         }
       }
@@ -377,6 +388,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(W, 8)))
       using R = typename Raw<ES>::type;
       constexpr int NROUND = (EH + NW) / NW;
       R raw[2][NPOP];
+      float keep0[NROUND];  // f_0 of image rows 1..TY, by round (P0 == 1)
       const auto task_xy = [&](int q, int &x, int &y) {
         x = q < EH ? lane + 1 : ((lane & 1) ? PAIR_W - 1 : 0);
         y = q < EH ? q : lane >> 1;
@@ -419,17 +431,19 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(W, 8)))
             for (int p = 0; p < NPOP; ++p) im.set(d, p, x, y, p < 9 ? f[p] : g[p - 9]);
             if (is_edge(d, i, j)) ghost_epilogue<C>(d, im, i, j, f, g, in1);
           }
+          if (P0 == 1) keep0[k] = storage_round<C>(d, 0, f[0]);
         }
       }
       __syncthreads();
       // step 2: the tile, from the image
-      for (int r = wave; r < TY; r += NW) {
+      const auto out_row = [&](int r, float f0) {
         const int i = ia + lane, j = ja + r;
         if ((i < nx) & (j < nr)) {
           float f[9], g[4];
+          f[0] = f0;
 #pragma unroll
-          for (int p = 0; p < NPOP; ++p) {
-            const float v = img[(p * EH + r + 1 - per(p)) * PAIR_W + lane + 1 - pex(p)];
+          for (int p = P0; p < NPOP; ++p) {
+            const float v = img[((p - P0) * EH + r + 1 - per(p)) * PAIR_W + lane + 1 - pex(p)];
             if (p < 9) f[p] = v; else g[p - 9] = v;
           }
           const float rr = d.r0 + (float)j + 0.5f;
@@ -438,6 +452,15 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(W, 8)))
           store_node<C, AUX_S>(d, rd, voff, plane_b, f, g);
           if (tile_edge && is_edge(d, i, j)) ghost_epilogue<C>(d, out, i, j, f, g, in2);
         }
+      };
+      if constexpr (P0 == 1) {
+#pragma unroll
+        for (int k = 0; k < NROUND; ++k) {
+          const int y = wave + NW * k;  // image row of step 1 -> tile row y - 1
+          if ((y >= 1) & (y <= TY)) out_row(y - 1, keep0[k]);
+        }
+      } else {
+        for (int r = wave; r < TY; r += NW) out_row(r, 0.0f);
       }
     }
     __syncthreads();  // the image is reused by the next tile

@@ -21,6 +21,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--copy-mib", type=int, default=256)
     ap.add_argument("--tile-shape", type=int, default=-1)
+    ap.add_argument("--layout", choices=["two", "single"], default="two")
     args = ap.parse_args()
     import torch
 
@@ -38,7 +39,7 @@ def main():
     else:
         p, inlet, _ = inputs.workload_large(n_t=max(1, args.steps))
     kw = {} if args.tile_shape < 0 else {"tile_shape": args.tile_shape}
-    with lbm.Solver(p, args.precision, **kw) as s:
+    with lbm.Solver(p, args.precision, layout=args.layout, **kw) as s:
         s.set_inlet(*inlet)
         s.step(args.steps)
         s.sync()

@@ -67,7 +67,8 @@ def test_pair_shapes_compiled():
     for q in pairs:
         inf = infos[q]
         assert inf["bx"] == 64 and inf["by"] in (4, 8) and inf["nx"] == 1
-        assert inf["lds"] == 13 * (inf["by"] * inf["ny"] + 2) * 66 * 4
+        planes = 12 if inf["cache"] & 8 else 13  # bit 3: f_0 kept in registers
+        assert inf["lds"] == planes * (inf["by"] * inf["ny"] + 2) * 66 * 4
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp16", "bf16"])
