@@ -174,8 +174,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                          "(the multi-GPU split is described in DESIGN.md, not built)"}))
+        print(json.dumps({"error": "bench.py measures one GPU; --gpus must be 1 (jets are "
+                          "independent, so several GPUs would each run their own share)"}))
         sys.exit(2)
 
     import torch

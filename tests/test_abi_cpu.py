@@ -114,3 +114,18 @@ def test_layout_validated_and_single_buffer_is_half(lib):
     cfg.abi_version = 1
     n = ctypes.c_size_t()
     assert lib.lbm_bytes_required(ctypes.byref(cfg), ctypes.byref(n)) == lbm.EINVAL
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; asking for more exits with a message (before
+    touching any device)."""
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in msg["error"]

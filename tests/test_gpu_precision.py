@@ -71,9 +71,14 @@ def _run_ref(p, inlet, steps):
 
 
 def _record(name, data):
-    os.makedirs(os.path.join(ROOT, "gpurun_out"), exist_ok=True)
-    with open(os.path.join(ROOT, "gpurun_out", "precision.jsonl"), "a") as fh:
-        fh.write(json.dumps({"case": name, **data}) + "\n")
+    """Print the measured errors (visible with pytest -s); with
+    LBM_PRECISION_LOG set, also append them to that file as JSON lines."""
+    line = json.dumps({"case": name, **data})
+    print(line)
+    path = os.environ.get("LBM_PRECISION_LOG")
+    if path:
+        with open(path, "a") as fh:
+            fh.write(line + "\n")
 
 
 def test_small_jet_16bit_storage():
