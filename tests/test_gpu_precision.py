@@ -21,7 +21,6 @@ from gpu_common import host_threads, rel_err, require_gpu, speed
 
 pytestmark = pytest.mark.gpu
 
-ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 @pytest.fixture(scope="module", autouse=True)
