@@ -22,7 +22,6 @@ from gpu_common import host_threads, rel_err, require_gpu, speed
 pytestmark = pytest.mark.gpu
 
 
-
 @pytest.fixture(scope="module", autouse=True)
 def _gpu():
     require_gpu()
