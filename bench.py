@@ -24,6 +24,12 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_NODE = {"fp32": 104, "fp16": 52, "bf16": 52}
+# Vector ALU issue: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz (a wave64 FP32
+# instruction every 4 cycles per SIMD; packed FP32 not used), lane-ops/s.
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# VALU instructions of one FP32 node update: the one-step kernel's hot path
+# (loads to stores) as compiled for gfx950.
+VALU_PER_UPDATE = 214
 
 
 def _ensure_built():
@@ -220,7 +226,12 @@ def main():
                      "bytes_per_node_per_launch": BYTES_PER_NODE["fp32"],
                      "kernel_ms_per_launch": round(ms_launch, 5),
                      "per_step_equivalent_GBps": round(
-                         BYTES_PER_NODE["fp32"] * nodes / (ms_step * 1e-3) / 1e9, 1)},
+                         BYTES_PER_NODE["fp32"] * nodes / (ms_step * 1e-3) / 1e9, 1),
+                     "alu": {"unit": "T lane-op/s", "peak": round(VALU_PEAK_TOPS, 2),
+                             "valu_per_node_update": VALU_PER_UPDATE,
+                             "achieved": round(VALU_PER_UPDATE * nodes / (ms_step * 1e-3) / 1e12, 2),
+                             "frac": round(VALU_PER_UPDATE * nodes / (ms_step * 1e-3) / 1e12 /
+                                           VALU_PEAK_TOPS, 4)}},
     }
     if not args.no_extra:
         extra = {}
