@@ -4,10 +4,14 @@ A step is one time step of the whole hot path (edge pulls, moments,
 properties, Smagorinsky relaxation time, sources, collision, store) over the
 2048 x 512 jet; the FP64 conservation check runs once per 1000 steps inside
 the timed region.  Throughput is GLUPS (lattice node updates per second /
-1e9).  The roofline is HBM bandwidth: a launch reads and writes every stored
-population once, 104 B per node for FP32 storage (13 populations) and 52 B
-for 16-bit storage, whether it advances one step or two (the LDS-blocked
-kernel); `achieved` divides those bytes by the measured launch duration.
+1e9).  The roofline is HBM bandwidth at the algorithmic 104 B per node update
+for FP32 storage (13 populations read and written) and 52 B for 16-bit
+storage: `achieved` = those bytes times the node updates of one launch,
+divided by the launch duration measured with HIP events.  A launch of the
+LDS-blocked kernel performs two node updates per node while it reads and
+writes each population once; the HBM bytes it actually moves (rocprofv3
+counters) are reported beside it as `traffic`, and their rate as
+`dram_GBps`.
 
 Prints one JSON line.  Also reports FP16- and BF16-deviation storage on the
 same jet, the 4096 x 1024 jet (a working set above the 256 MB Infinity
@@ -199,7 +203,9 @@ def main():
     wall, ms_step, _ = time_jet(p, inlet, "fp32", args.steps, args.warmup, tile_shape=shape)
     glups = nodes * args.steps / wall / 1e9
     ms_launch = ms_step * info["steps"]
-    achieved = BYTES_PER_NODE["fp32"] * nodes / (ms_launch * 1e-3) / 1e9
+    updates_per_launch = nodes * info["steps"]
+    alg_bytes = BYTES_PER_NODE["fp32"] * updates_per_launch
+    achieved = alg_bytes / (ms_launch * 1e-3) / 1e9
     traffic = read_traffic(f"traffic_{kernel_of(info).split('_')[0]}_fp32_2048x512.txt")
     line = {
         "metric": "GLUPS & % HBM peak, FP32 vs FP16-storage; batched-jet p50/p99 solve latency",
@@ -223,10 +229,12 @@ def main():
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic, "kernel": kernel_of(info),
                      "steps_per_launch": info["steps"],
-                     "bytes_per_node_per_launch": BYTES_PER_NODE["fp32"],
+                     "node_updates_per_launch": updates_per_launch,
+                     "bytes_per_node_update": BYTES_PER_NODE["fp32"],
+                     "algorithmic_bytes_per_launch": alg_bytes,
                      "kernel_ms_per_launch": round(ms_launch, 5),
-                     "per_step_equivalent_GBps": round(
-                         BYTES_PER_NODE["fp32"] * nodes / (ms_step * 1e-3) / 1e9, 1),
+                     "dram_GBps": (round(traffic / (ms_launch * 1e-3) / 1e9, 1)
+                                   if traffic else None),
                      "alu": {"unit": "T lane-op/s", "peak": round(VALU_PEAK_TOPS, 2),
                              "valu_per_node_update": VALU_PER_UPDATE,
                              "achieved": round(VALU_PER_UPDATE * nodes / (ms_step * 1e-3) / 1e12, 2),
@@ -238,10 +246,11 @@ def main():
         steps_x = max(200, args.steps // 4)
 
         def entry(prec, q, w, ms, n_nodes, n_steps):
+            # ms: per step; algorithmic bytes per node update over the step time
             inf = lbm.tile_shape_info(q)
             return {"glups": round(n_nodes * n_steps / w / 1e9, 3), "tile_shape": inf,
                     "hbm_frac": round(BYTES_PER_NODE[prec] * n_nodes /
-                                      (ms * inf["steps"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+                                      (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
         # the same jet with one step per launch (the best one-step shape)
         q1 = autotune.best_shape(p, inlet, "fp32", steps=1)
