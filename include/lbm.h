@@ -214,8 +214,10 @@ void lbm_batch_destroy(lbm_batch *b);
 int lbm_tile_shape_count(void);
 int lbm_tile_shape(int32_t index, int32_t *bx, int32_t *by, int32_t *ny, int32_t *nx);
 /* All properties of a shape: info[0..n-1] of (bx, by, ny, nx, waves per SIMD
- * targeted, cache policy (bit 0 non-temporal stores, bit 1 loads), steps per
- * launch, LDS bytes per workgroup); n <= 8 entries are written.
+ * targeted, variant bits (bit 0 non-temporal stores, bit 1 non-temporal
+ * loads; two-step shapes: bit 2 no prefetch of the next rows' loads, bit 3
+ * f_0 kept in registers instead of LDS), steps per launch, LDS bytes per
+ * workgroup); n <= 8 entries are written.
  * Shapes with 2 steps per launch run two time steps of eq. (1) per kernel
  * launch on an LDS-resident 64 x (by * ny) tile with a one-node frame,
  * bit-identical to two one-step launches; they reject jets with periodic
