@@ -203,7 +203,8 @@ int lbm_batch_jet_bytes(const lbm_batch *b, const lbm_config *cfg, size_t *bytes
 int lbm_batch_active(const lbm_batch *b, int32_t *n_active, size_t *bytes_used);
 /* Tile shape of the step kernel (index into the compiled shapes; -1 = auto;
  * a two-step shape is used only while no active jet has periodic edges) and
- * the number of persistent workgroups (0 = auto). */
+ * the number of persistent workgroups (0 = auto: as many as the device holds
+ * at once for that kernel). */
 int lbm_batch_set_launch(lbm_batch *b, int32_t tile_shape, int32_t workgroups);
 /* Cohort size limit in bytes of population buffers (0: all jets together). */
 int lbm_batch_set_cohort_bytes(lbm_batch *b, size_t bytes);

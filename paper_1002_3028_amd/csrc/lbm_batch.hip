@@ -164,8 +164,10 @@ int rebuild(lbm_batch *b) {
   const int32_t nh = std::max(prev, b->n_cohorts);
   if (nh > 0)
     LBM_HIP(hipMemcpy(b->d_hdr, hdr.data(), nh * sizeof(BatchHdr), hipMemcpyHostToDevice));
-  // persistent grid: enough workgroups to fill the chip several times over
-  int32_t g = b->wg > 0 ? b->wg : 2048;
+  // persistent grid of fixed size (graphs stay valid as jets come and go):
+  // by default the workgroups the device holds at once
+  int32_t g = b->wg > 0 ? b->wg
+                        : resident_workgroups(shape, b->prec, b->layout == LBM_LAYOUT_SINGLE);
   g = (g + 7) / 8 * 8;
   b->grid = g;
   b->cur_shape = shape;

@@ -187,15 +187,32 @@ int launch_step(int shape, int prec, int grid, hipStream_t st, const JetDesc *je
   return LBM_OK;
 }
 
-int launch_aa_step(int prec, int grid, hipStream_t st, const JetDesc *jets, const int32_t *tiles,
-                   const BatchHdr *hdr, int32_t koff, int32_t *flags) {
+static const void *aa_fn(int prec) {
   static const void *fn[3] = {(const void *)&aa_kernel<CodecF32>,
                               (const void *)&aa_kernel<CodecF16>,
                               (const void *)&aa_kernel<CodecBF16>};
+  return fn[codec_index(prec)];
+}
+
+int resident_workgroups(int shape, int prec, bool single_buffer) {
+  const TileShape &s = kShapes[shape];
+  const void *fn = single_buffer ? aa_fn(prec) : s.fn[codec_index(prec)];
+  const int threads = single_buffer ? 256 : s.bx * s.by;
+  int per_cu = 0, cus = 0, dev = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, threads, 0) != hipSuccess ||
+      hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      per_cu <= 0 || cus <= 0)
+    return 2048;
+  return (per_cu * cus + 7) / 8 * 8;
+}
+
+int launch_aa_step(int prec, int grid, hipStream_t st, const JetDesc *jets, const int32_t *tiles,
+                   const BatchHdr *hdr, int32_t koff, int32_t *flags) {
   int32_t tog = 0, nsteps = 1;
   void *args[] = {(void *)&jets, (void *)&tiles, (void *)&hdr,   (void *)&koff,
                   (void *)&tog,  (void *)&nsteps, (void *)&flags};
-  LBM_HIP(hipLaunchKernel(fn[codec_index(prec)], dim3(grid), dim3(64, 4), args, 0, st));
+  LBM_HIP(hipLaunchKernel(aa_fn(prec), dim3(grid), dim3(64, 4), args, 0, st));
   return LBM_OK;
 }
 

@@ -99,6 +99,10 @@ int launch_encode(int prec, hipStream_t st, const JetDesc *d, const lbm_config *
 
 int tiles_of(const lbm_config *c, int shape, int32_t *tiles_x);
 
+// Workgroups of the step kernel of `shape` (or of the single-buffer kernel)
+// that the current device holds at once: one full wave of a persistent grid.
+int resident_workgroups(int shape, int prec, bool single_buffer);
+
 // Simple device scratch that grows on demand.
 struct Scratch {
   void *p = nullptr;
