@@ -163,10 +163,13 @@ __device__ __forceinline__ float proj(int ex, int er, float vx, float vr) {
   return (ex > 0 ? vx : -vx) + (er > 0 ? vr : -vr);
 }
 
+// Written as w rho (b + eu (3 + 4.5 eu)), b = 1 - 1.5 u.u shared by all
+// links: three instructions per link (plus the sum for a diagonal).
 __device__ __forceinline__ float feq_link(int k, float rho, float ux, float ur) {
+  const float base = 1.0f - 1.5f * (ux * ux + ur * ur);
+  if (k == 0) return w9(0) * rho * base;
   const float eu = proj(ex9(k), er9(k), ux, ur);
-  const float uu = ux * ux + ur * ur;
-  return w9(k) * rho * (1.0f + 3.0f * eu + 4.5f * eu * eu - 1.5f * uu);
+  return (w9(k) * rho) * __builtin_fmaf(eu, __builtin_fmaf(4.5f, eu, 3.0f), base);
 }
 __device__ __forceinline__ float geq_link(int k, float T, float ux, float ur) {
   const float eu = proj(ex4(k), er4(k), ux, ur);
@@ -197,33 +200,24 @@ template <class H = NoHook>
 __device__ __forceinline__ bool collide(const JetDesc &d, float rinv, float r2,
                                         float (&f)[9], float (&g)[4], const H &hook = H()) {
   // eq. (2)
-  const float rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
-  const float mx = (f[1] + f[5] + f[8]) - (f[3] + f[6] + f[7]);
-  const float mr = (f[2] + f[5] + f[6]) - (f[4] + f[7] + f[8]);
+  // (partial sums shared between rho, m and Q)
+  const float s13 = f[1] + f[3], s24 = f[2] + f[4];
+  const float s58 = f[5] + f[8], s67 = f[6] + f[7];
+  const float sd = s58 + s67;  // the four diagonal links
+  const float rho = ((f[0] + s13) + s24) + sd;
+  const float mx = (f[1] - f[3]) + (s58 - s67);
+  const float mr = (f[2] - f[4]) + ((f[5] + f[6]) - (f[7] + f[8]));
   const float T = (g[0] + g[1]) + (g[2] + g[3]);
   const float irho = fast_rcp(rho);
   const float ux = mx * irho, ur = mr * irho;
 
-  // eq. (4): Q_ij = sum_k e_ki e_kj (f_k - f_k^eq)
-  float feq[9];
-#pragma unroll
-  for (int k = 0; k < 9; ++k) feq[k] = feq_link(k, rho, ux, ur);
-  // (sums start from their first term: no addition of a zero)
-  float qxx = 0.f, qrr = 0.f, qxr = 0.f;
-  bool hx = false, hr = false, hxr = false;
-#pragma unroll
-  for (int k = 1; k < 9; ++k) {
-    const float fn = f[k] - feq[k];
-    if (ex9(k) != 0) { qxx = hx ? qxx + fn : fn; hx = true; }
-    if (er9(k) != 0) { qrr = hr ? qrr + fn : fn; hr = true; }
-    if (ex9(k) * er9(k) != 0) {
-      const bool pos = ex9(k) * er9(k) > 0;
-      qxr = hxr ? (pos ? qxr + fn : qxr - fn) : (pos ? fn : -fn);
-      hxr = true;
-    }
-  }
-  // sum_k e_kr g_k^neq (the links +r and -r)
-  const float jr = (g[1] - geq_link(1, T, ux, ur)) - (g[3] - geq_link(3, T, ux, ur));
+  // eq. (4): Q_ij = sum_k e_ki e_kj (f_k - f_k^eq), with the second moments of
+  // the equilibrium in closed form: rho/3 delta_ij + rho u_i u_j
+  const float qxx = (s13 + sd) - rho * __builtin_fmaf(ux, ux, 1.0f / 3.0f);
+  const float qrr = (s24 + sd) - rho * __builtin_fmaf(ur, ur, 1.0f / 3.0f);
+  const float qxr = ((f[5] + f[7]) - (f[6] + f[8])) - mx * ur;
+  // sum_k e_kr g_k^neq = (g_+r - g_-r) - T u_r
+  const float jr = (g[1] - g[3]) - T * ur;
 
   // eq. (6): multiplier tables, linear on a uniform grid, clamped
   float x = fmaxf((T - d.t_lo) * d.t_scale, 0.0f);  // NaN -> 0
@@ -259,15 +253,18 @@ __device__ __forceinline__ bool collide(const JetDesc &d, float rinv, float r2,
   const float Fr = (-rho * ur * ur - kv * qrr) * rinv - 2.0f * rho * nu_tot * ur * hden;
   const float S = (-T * ur - ka * jr) * rinv;
 
-  // eq. (1)
+  // eq. (1), as f (1 - 1/tau) + f^eq / tau + source
   const float fx6 = Fx * (1.0f / 6.0f), fr6 = Fr * (1.0f / 6.0f);
+  const float omf = 1.0f - itau, omg = 1.0f - itau_a;
 #pragma unroll
   for (int k = 0; k < 9; ++k)
-    f[k] = f[k] - (f[k] - feq[k]) * itau +
-           (w9(k) * theta + proj(ex9(k), er9(k), fx6, fr6));
+    f[k] = __builtin_fmaf(f[k], omf,
+                          __builtin_fmaf(feq_link(k, rho, ux, ur), itau,
+                                         w9(k) * theta + proj(ex9(k), er9(k), fx6, fr6)));
   const float s4 = 0.25f * S;
 #pragma unroll
-  for (int k = 0; k < 4; ++k) g[k] = g[k] - (g[k] - geq_link(k, T, ux, ur)) * itau_a + s4;
+  for (int k = 0; k < 4; ++k)
+    g[k] = __builtin_fmaf(g[k], omg, __builtin_fmaf(geq_link(k, T, ux, ur), itau_a, s4));
 
   return (rho > 0.0f) && (rho < __builtin_inff()) && (fabsf(T) < __builtin_inff());
 }
