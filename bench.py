@@ -33,7 +33,7 @@ BYTES_PER_NODE = {"fp32": 104, "fp16": 52, "bf16": 52}
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # VALU instructions of one FP32 node update: the one-step kernel's hot path
 # (loads to stores) as compiled for gfx950.
-VALU_PER_UPDATE = 214
+VALU_PER_UPDATE = 185
 
 
 def _ensure_built():
