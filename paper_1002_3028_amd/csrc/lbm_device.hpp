@@ -211,15 +211,8 @@ __device__ __forceinline__ bool collide(const JetDesc &d, float rinv, float r2,
   const float irho = fast_rcp(rho);
   const float ux = mx * irho, ur = mr * irho;
 
-  // eq. (4): Q_ij = sum_k e_ki e_kj (f_k - f_k^eq), with the second moments of
-  // the equilibrium in closed form: rho/3 delta_ij + rho u_i u_j
-  const float qxx = (s13 + sd) - rho * __builtin_fmaf(ux, ux, 1.0f / 3.0f);
-  const float qrr = (s24 + sd) - rho * __builtin_fmaf(ur, ur, 1.0f / 3.0f);
-  const float qxr = ((f[5] + f[7]) - (f[6] + f[8])) - mx * ur;
-  // sum_k e_kr g_k^neq = (g_+r - g_-r) - T u_r
-  const float jr = (g[1] - g[3]) - T * ur;
-
-  // eq. (6): multiplier tables, linear on a uniform grid, clamped
+  // eq. (6): multiplier tables, linear on a uniform grid, clamped; the gather
+  // goes out first, the work below that does not need it hides its latency
   float x = fmaxf((T - d.t_lo) * d.t_scale, 0.0f);  // NaN -> 0
   x = fminf(x, (float)(d.table_n - 1));
   const int i0 = max(min((int)x, d.table_n - 2), 0);
@@ -231,12 +224,28 @@ __device__ __forceinline__ bool collide(const JetDesc &d, float rinv, float r2,
     hook();
     __builtin_amdgcn_sched_barrier(0);
   }
+
+  // equilibria (eq. 2 moments)
+  float feq[9], geq[4];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) feq[k] = feq_link(k, rho, ux, ur);
+#pragma unroll
+  for (int k = 0; k < 4; ++k) geq[k] = geq_link(k, T, ux, ur);
+
+  // eq. (4): Q_ij = sum_k e_ki e_kj (f_k - f_k^eq), with the second moments of
+  // the equilibrium in closed form: rho/3 delta_ij + rho u_i u_j
+  const float qxx = (s13 + sd) - rho * __builtin_fmaf(ux, ux, 1.0f / 3.0f);
+  const float qrr = (s24 + sd) - rho * __builtin_fmaf(ur, ur, 1.0f / 3.0f);
+  const float qxr = ((f[5] + f[7]) - (f[6] + f[8])) - mx * ur;
+  // sum_k e_kr g_k^neq = (g_+r - g_-r) - T u_r
+  const float jr = (g[1] - g[3]) - T * ur;
+  const float qn = fast_sqrt(2.0f * (qxx * qxx + 2.0f * qxr * qxr + qrr * qrr));
+
   const float nu = d.nu0 * (te.x + w * te.y);
   const float alpha = d.alpha0 * (te.z + w * te.w);
   const float tau_nu = 0.5f + 3.0f * nu;
 
   // eq. (4): local relaxation time
-  const float qn = fast_sqrt(2.0f * (qxx * qxx + 2.0f * qxr * qxr + qrr * qrr));
   const float tau = 0.5f * (tau_nu + fast_sqrt(tau_nu * tau_nu + d.c18 * qn * irho));
   // eqs. (3), (5)
   const float nu_tot = (tau - 0.5f) * (1.0f / 3.0f);
@@ -259,12 +268,12 @@ __device__ __forceinline__ bool collide(const JetDesc &d, float rinv, float r2,
 #pragma unroll
   for (int k = 0; k < 9; ++k)
     f[k] = __builtin_fmaf(f[k], omf,
-                          __builtin_fmaf(feq_link(k, rho, ux, ur), itau,
+                          __builtin_fmaf(feq[k], itau,
                                          w9(k) * theta + proj(ex9(k), er9(k), fx6, fr6)));
   const float s4 = 0.25f * S;
 #pragma unroll
   for (int k = 0; k < 4; ++k)
-    g[k] = __builtin_fmaf(g[k], omg, __builtin_fmaf(geq_link(k, T, ux, ur), itau_a, s4));
+    g[k] = __builtin_fmaf(g[k], omg, __builtin_fmaf(geq[k], itau_a, s4));
 
   return (rho > 0.0f) && (rho < __builtin_inff()) && (fabsf(T) < __builtin_inff());
 }
