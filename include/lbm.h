@@ -111,7 +111,10 @@ typedef struct {
 } lbm_config;
 
 /* Device bytes lbm_create_in needs for the population buffers (two, or one
- * with LBM_LAYOUT_SINGLE). */
+ * with LBM_LAYOUT_SINGLE).  Kernels address a buffer with 32-bit byte
+ * offsets: a grid whose 13 FP32 planes, each (nx + 73 rounded up to 64) x
+ * (nr + 2) including the ghost ring, reach 2^31 bytes is LBM_EINVAL here and
+ * in lbm_create (8192 x 4096 fits, 10000 x 5000 does not). */
 int lbm_bytes_required(const lbm_config *cfg, size_t *bytes);
 
 /* Create a solver on the current HIP device, populations at the
