@@ -76,12 +76,17 @@ def test_profiles_are_moment_slices():
     np.testing.assert_allclose(pr["T_exit"], m["T"][:, -1], rtol=1e-6, atol=1e-9)
 
 
-def test_runaway_inlet_reports_unstable():
-    """A supersonic inlet blows the jet up; the step kernel flags it and the
-    next synchronising call reports LBM_EUNSTABLE, sticky until a new state."""
+@pytest.mark.parametrize("kernel", ["one_step", "two_steps", "single_buffer"])
+def test_runaway_inlet_reports_unstable(kernel):
+    """A supersonic inlet blows the jet up; every kernel (one or two steps
+    per launch, single buffer) flags it and the next synchronising call
+    reports LBM_EUNSTABLE, sticky until a new state."""
     from paper_1002_3028_amd import inputs, lbm
     p = tiny_params(64, 16, "jet", 0)
-    with lbm.Solver(p, "fp32") as s:
+    pair = [q for q, i in enumerate(lbm.tile_shape_infos()) if i["steps"] == 2][0]
+    kw = {"one_step": dict(tile_shape=0), "two_steps": dict(tile_shape=pair, graph_steps=10),
+          "single_buffer": dict(layout="single")}[kernel]
+    with lbm.Solver(p, "fp32", **kw) as s:
         s.set_inlet(*inputs.inlet_rows(16, 8.0, 0.9, 5.0))
         s.step(400)
         assert s.try_sync() == lbm.EUNSTABLE
