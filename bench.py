@@ -155,6 +155,31 @@ def bench_serving(n_requests=200, precision="fp16"):
             "glups_at_rate": run["glups"]}
 
 
+def copy_ceiling(nbytes, reps=50):
+    """A plain 16-byte-per-lane copy of nbytes into another nbytes (read +
+    write = 2 nbytes moved), timed with HIP events: the streaming rate a
+    kernel that reads one buffer and writes another can hope for."""
+    import torch
+    from paper_1002_3028_amd import lbm
+
+    nbytes = nbytes // 256 * 256
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    st = torch.cuda.current_stream()
+    for _ in range(3):
+        lbm.probe_copy(b.data_ptr(), a.data_ptr(), nbytes, st.cuda_stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        lbm.probe_copy(b.data_ptr(), a.data_ptr(), nbytes, st.cuda_stream)
+    e1.record(st)
+    st.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    return {"bytes_per_buffer": nbytes, "us": round(ms * 1e3, 2),
+            "GBps": round(2 * nbytes / (ms * 1e-3) / 1e9, 1),
+            "frac_of_peak": round(2 * nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 def cpu_baseline(params, inlet, budget_s=12.0):
     import oracle
 
@@ -175,6 +200,50 @@ def cpu_baseline(params, inlet, budget_s=12.0):
                       f"(FP64, OpenMP over radial rows), {dt:.1f} s"}
 
 
+def oracle_timing():
+    """The FP64 oracle on one thread and on every host core (OpenMP over radial
+    rows; bit-identical results for any thread count): the 128 x 32 jet for
+    its 500 steps, the first 200 steps of the 2048 x 512 jet and 100 steps of
+    the 1024 x 256 twin of the 4096 x 1024 jet, warm (after two steps), median
+    of three for runs under a second."""
+    import platform
+    import oracle
+    from paper_1002_3028_amd import inputs
+
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")),
+                         "")
+    except OSError:
+        pass
+    cores = max(1, min(16, os.cpu_count() or 1))
+    cases = [("128x32 jet, 500 steps", inputs.workload_small()[:2], 500),
+             ("2048x512 jet, first 200 steps", inputs.workload_single(n_t=200)[:2], 200),
+             ("1024x256 twin, 100 steps", inputs.workload_large(1024, 256, n_t=100)[:2], 100)]
+    rows = []
+    for name, (p, inlet), steps in cases:
+        nodes = p["nx"] * p["nr"]
+        for threads in (1, cores):
+            times = []
+            for _ in range(3):
+                with oracle.RefSolver(p, threads=threads) as ref:
+                    ref.set_inlet(*inlet)
+                    ref.step(2)
+                    t = time.perf_counter()
+                    ref.step(steps)
+                    times.append(time.perf_counter() - t)
+                if times[-1] > 1.0:
+                    break
+            dt = sorted(times)[len(times) // 2]
+            rows.append({"case": name, "threads": threads, "seconds": round(dt, 3),
+                         "mlups": round(nodes * steps / dt / 1e6, 2)})
+            print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    return {"oracle_timing": rows,
+            "host": {"cpu": model, "nproc": os.cpu_count(), "machine": platform.machine(),
+                     "compiler": "gcc -O2 -std=c11 -ffp-contract=off -fopenmp"}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -182,7 +251,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=500)
     ap.add_argument("--no-extra", action="store_true", help="headline workload only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--oracle-timing", action="store_true",
+                    help="only time the FP64 oracle (1 thread and all cores) and exit")
     args = ap.parse_args()
+    if args.oracle_timing:
+        print(json.dumps(oracle_timing()))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "bench.py measures one GPU; --gpus must be 1 (jets are "
                           "independent, so several GPUs would each run their own share)"}))
@@ -276,6 +350,9 @@ def main():
                 "bytes": lbm.bytes_required(pp, "fp32", "single"),
                 "two_buffer_bytes": lbm.bytes_required(pp, "fp32", "two"),
                 "hbm_frac": round(BYTES_PER_NODE["fp32"] * nn / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        # practical streaming ceiling: a plain copy of each jet's two-buffer footprint
+        extra["copy_kernel"] = {tag: copy_ceiling(lbm.bytes_required(pp, "fp32", "two") // 2)
+                                for tag, pp in (("2048x512_fp32", p), ("4096x1024_fp32", pl))}
         extra["batch_64_jets"] = bench_batch()
         extra["serving_fp16"] = bench_serving(precision="fp16")
         extra["serving_fp32"] = bench_serving(precision="fp32")
