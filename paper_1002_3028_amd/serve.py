@@ -120,19 +120,30 @@ def main():
     ap.add_argument("--k", type=int, default=50)
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--layout", choices=["two", "single"], default="two")
+    ap.add_argument("--sweep", default="",
+                    help="comma-separated fractions of the measured capacity to run at "
+                         "(e.g. 0.3,0.5,0.7,0.9); overrides --rate")
     args = ap.parse_args()
     budget = int(args.budget_gb * (1 << 30))
     rate = args.rate
-    if rate <= 0:
+    cap = None
+    if rate <= 0 or args.sweep:
         cap, _ = serve(inputs.arrival_trace(args.requests, args.seed, rate=1.0), args.precision,
                        budget, args.slots, args.k, realtime=False, layout=args.layout)
         print(json.dumps({"saturated": cap}), flush=True)
-        rate = 0.7 * cap["requests_per_s"]
-    trace = inputs.arrival_trace(args.requests, args.seed, rate=rate)
-    summary, _ = serve(trace, args.precision, budget, args.slots, args.k, realtime=True,
-                       layout=args.layout)
-    summary["rate"] = rate
-    print(json.dumps({"poisson": summary}), flush=True)
+    fractions = [float(x) for x in args.sweep.split(",") if x] if args.sweep else [None]
+    for frac in fractions:
+        if frac is not None:
+            rate = frac * cap["requests_per_s"]
+        elif rate <= 0:
+            rate = 0.7 * cap["requests_per_s"]
+        trace = inputs.arrival_trace(args.requests, args.seed, rate=rate)
+        summary, _ = serve(trace, args.precision, budget, args.slots, args.k, realtime=True,
+                           layout=args.layout)
+        summary["rate"] = rate
+        if frac is not None:
+            summary["fraction_of_capacity"] = frac
+        print(json.dumps({"poisson": summary}), flush=True)
 
 
 if __name__ == "__main__":
