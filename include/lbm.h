@@ -209,8 +209,18 @@ int lbm_batch_active(const lbm_batch *b, int32_t *n_active, size_t *bytes_used);
  * the number of persistent workgroups (0 = auto: as many as the device holds
  * at once for that kernel). */
 int lbm_batch_set_launch(lbm_batch *b, int32_t tile_shape, int32_t workgroups);
-/* Cohort size limit in bytes of population buffers (0: all jets together). */
+/* Cohort size limit in bytes of population buffers (0: all jets together;
+ * default 112 MiB, so that the two cohorts running at once fit the 256 MB
+ * Infinity Cache). */
 int lbm_batch_set_cohort_bytes(lbm_batch *b, size_t bytes);
+/* Streams the cohorts of a run are spread over: 1 (the batch's stream) or 2
+ * (the default: odd cohorts on a second stream of default priority that the
+ * library creates; it starts after the work already queued on the batch's
+ * stream, and later work on the batch's stream waits for it, so callers see
+ * one stream).  Results are the same bits either way.  Synchronises;
+ * LBM_EINVAL for other values, LBM_EDEVICE (and one stream) if the second
+ * stream cannot be created. */
+int lbm_batch_set_streams(lbm_batch *b, int32_t n);
 void lbm_batch_destroy(lbm_batch *b);
 
 /* Compiled tile shapes of the step kernel: count, and one shape: a workgroup

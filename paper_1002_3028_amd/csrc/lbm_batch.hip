@@ -84,7 +84,9 @@ struct lbm_batch {
   BatchHdr *d_hdr = nullptr;       // per cohort: number of jets
   int32_t max_cohorts = 0;
   int32_t n_cohorts = 0;
-  size_t cohort_bytes = size_t(200) << 20;  // 0: one cohort
+  // 0: one cohort.  Two cohorts run at once (two streams), and together they
+  // stay inside the 256 MB Infinity Cache.
+  size_t cohort_bytes = size_t(112) << 20;
   int32_t *d_flags = nullptr;
   Scratch scratch;
   std::vector<int32_t> active;  // slots in the compact list, in order
@@ -94,6 +96,11 @@ struct lbm_batch {
   int32_t wg = 0;       // 0: auto
   int32_t grid = 0;
   std::map<std::tuple<int, int, int, int>, hipGraphExec_t> graphs;  // (k, shape, grid, cohort)
+  // cohorts alternate between the batch's stream and a second one, so that
+  // one cohort's launches fill the device while the other's start or drain
+  int32_t nstreams = 2;
+  hipStream_t side = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
 };
 
 namespace {
@@ -175,7 +182,7 @@ int rebuild(lbm_batch *b) {
   return LBM_OK;
 }
 
-int run_group(lbm_batch *b, int32_t k, int32_t c) {
+int run_group(lbm_batch *b, int32_t k, int32_t c, hipStream_t st) {
   const int shape = b->cur_shape;
   int nsh;
   const int32_t np = tile_shapes(&nsh)[shape].steps == 2 ? k / 2 : 0;
@@ -208,7 +215,7 @@ int run_group(lbm_batch *b, int32_t k, int32_t c) {
     if (ei != hipSuccess) return LBM_EDEVICE;
     it = b->graphs.emplace(key, ex).first;
   }
-  LBM_HIP(hipGraphLaunch(it->second, b->stream));
+  LBM_HIP(hipGraphLaunch(it->second, st));
   return LBM_OK;
 }
 
@@ -265,6 +272,8 @@ int lbm_batch_create(size_t budget_bytes, int32_t max_slots, int32_t precision,
     return LBM_ENOMEM;
   }
   b->arena.reset(b->budget);
+  // the second stream of the default two; one stream if it cannot be had
+  if (lbm_batch_set_streams(b, 2) != LBM_OK) b->nstreams = 1;
   *out = b;
   return LBM_OK;
 }
@@ -377,8 +386,19 @@ int lbm_batch_run(lbm_batch *b, int32_t k_steps) {
   int rc;
   if (b->dirty && (rc = rebuild(b))) return rc;
   if (b->active.empty()) return LBM_OK;
+  const bool two = b->nstreams == 2 && b->n_cohorts > 1;
+  if (two) {
+    // the second stream starts after everything queued so far
+    LBM_HIP(hipEventRecord(b->fork, b->stream));
+    LBM_HIP(hipStreamWaitEvent(b->side, b->fork, 0));
+  }
   for (int32_t c = 0; c < b->n_cohorts; ++c)
-    if ((rc = run_group(b, k_steps, c))) return rc;
+    if ((rc = run_group(b, k_steps, c, two && (c & 1) ? b->side : b->stream))) return rc;
+  if (two) {
+    // and everything queued later on the batch's stream waits for it
+    LBM_HIP(hipEventRecord(b->join, b->side));
+    LBM_HIP(hipStreamWaitEvent(b->stream, b->join, 0));
+  }
   // mirror of the advance kernel: every pair a jet took in full toggled its flip
   int nsh;
   const int64_t np = tile_shapes(&nsh)[b->cur_shape].steps == 2 ? k_steps / 2 : 0;
@@ -508,9 +528,32 @@ int lbm_batch_set_launch(lbm_batch *b, int32_t tile_shape, int32_t workgroups) {
   return LBM_OK;
 }
 
+int lbm_batch_set_streams(lbm_batch *b, int32_t n) {
+  if (!b || (n != 1 && n != 2)) return LBM_EINVAL;
+  LBM_HIP(hipStreamSynchronize(b->stream));
+  if (b->side) LBM_HIP(hipStreamSynchronize(b->side));
+  if (n == 2 && !b->side) {
+    const bool ok = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) == hipSuccess &&
+                    hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) == hipSuccess &&
+                    hipEventCreateWithFlags(&b->join, hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+      if (b->fork) (void)hipEventDestroy(b->fork);
+      if (b->join) (void)hipEventDestroy(b->join);
+      if (b->side) (void)hipStreamDestroy(b->side);
+      b->fork = b->join = nullptr;
+      b->side = nullptr;
+      b->nstreams = 1;
+      return LBM_EDEVICE;
+    }
+  }
+  b->nstreams = n;
+  return LBM_OK;
+}
+
 void lbm_batch_destroy(lbm_batch *b) {
   if (!b) return;
   if (b->stream) (void)hipStreamSynchronize(b->stream);
+  if (b->side) (void)hipStreamSynchronize(b->side);
   drop_graphs(b);
   for (Slot &s : b->slots) {
     if (s.d_table) (void)hipFree(s.d_table);
@@ -524,6 +567,9 @@ void lbm_batch_destroy(lbm_batch *b) {
   if (b->d_hdr) (void)hipFree(b->d_hdr);
   if (b->d_flags) (void)hipFree(b->d_flags);
   if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+  if (b->fork) (void)hipEventDestroy(b->fork);
+  if (b->join) (void)hipEventDestroy(b->join);
+  if (b->side) (void)hipStreamDestroy(b->side);
   delete b;
 }
 

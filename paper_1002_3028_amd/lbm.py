@@ -94,6 +94,7 @@ _SIGS = {
                          ctypes.c_int),
     "lbm_batch_set_launch": ([_vp, ctypes.c_int32, ctypes.c_int32], ctypes.c_int),
     "lbm_batch_set_cohort_bytes": ([_vp, ctypes.c_size_t], ctypes.c_int),
+    "lbm_batch_set_streams": ([_vp, ctypes.c_int32], ctypes.c_int),
     "lbm_batch_set_layout": ([_vp, ctypes.c_int32], ctypes.c_int),
     "lbm_batch_destroy": ([_vp], None),
     "lbm_tile_shape_count": ([], ctypes.c_int),
@@ -440,6 +441,10 @@ class Batch:
 
     def set_cohort_bytes(self, nbytes: int):
         _check(self.lib.lbm_batch_set_cohort_bytes(self.b, int(nbytes)), "lbm_batch_set_cohort_bytes")
+
+    def set_streams(self, n: int):
+        """Spread each run's cohorts over 1 or 2 streams."""
+        _check(self.lib.lbm_batch_set_streams(self.b, int(n)), "lbm_batch_set_streams")
 
     def set_launch(self, tile_shape: int = -1, workgroups: int = 0):
         _check(self.lib.lbm_batch_set_launch(self.b, int(tile_shape), int(workgroups)),

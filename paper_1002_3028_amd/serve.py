@@ -35,13 +35,14 @@ def percentile(xs, q):
 def serve(requests, precision: str = "fp16", budget_bytes: int = 16 << 30,
           max_slots: int = 256, k_steps: int = 50, realtime: bool = True,
           tile_shape: int = -1, workgroups: int = 0, keep_profiles: bool = False,
-          layout: str = "two"):
+          layout: str = "two", streams: int = 0, cohort_bytes: int = -1):
     """Run the request list [(arrival_s, params, inlet, steps), ...].
     layout="single" keeps each resident jet in one buffer updated in place,
     so a budget holds twice as many jets.
 
     realtime=False admits every request at t = 0 (saturation: measures the
-    capacity).  Returns a summary dict, plus per-request records.
+    capacity).  streams (1 or 2) and cohort_bytes override the batch's
+    defaults when given.  Returns a summary dict, plus per-request records.
     """
     order = sorted(range(len(requests)), key=lambda q: requests[q][0])
     pending = collections.deque(order)
@@ -53,6 +54,10 @@ def serve(requests, precision: str = "fp16", budget_bytes: int = 16 << 30,
     peak_bytes = 0
     with lbm.Batch(budget_bytes, max_slots, precision, layout=layout) as b:
         b.set_launch(tile_shape, workgroups)
+        if streams:
+            b.set_streams(streams)
+        if cohort_bytes >= 0:
+            b.set_cohort_bytes(cohort_bytes)
         t0 = time.perf_counter()
 
         def now():
@@ -120,16 +125,21 @@ def main():
     ap.add_argument("--k", type=int, default=50)
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--layout", choices=["two", "single"], default="two")
+    ap.add_argument("--streams", type=int, default=0, help="1 or 2 (0: the batch's default)")
+    ap.add_argument("--cohort-mib", type=int, default=-1,
+                    help="cohort limit in MiB (-1: the batch's default, 0: one cohort)")
     ap.add_argument("--sweep", default="",
                     help="comma-separated fractions of the measured capacity to run at "
                          "(e.g. 0.3,0.5,0.7,0.9); overrides --rate")
     args = ap.parse_args()
     budget = int(args.budget_gb * (1 << 30))
+    cohort = args.cohort_mib << 20 if args.cohort_mib >= 0 else -1
     rate = args.rate
     cap = None
     if rate <= 0 or args.sweep:
         cap, _ = serve(inputs.arrival_trace(args.requests, args.seed, rate=1.0), args.precision,
-                       budget, args.slots, args.k, realtime=False, layout=args.layout)
+                       budget, args.slots, args.k, realtime=False, layout=args.layout,
+                       streams=args.streams, cohort_bytes=cohort)
         print(json.dumps({"saturated": cap}), flush=True)
     fractions = [float(x) for x in args.sweep.split(",") if x] if args.sweep else [None]
     for frac in fractions:
@@ -139,7 +149,7 @@ def main():
             rate = 0.7 * cap["requests_per_s"]
         trace = inputs.arrival_trace(args.requests, args.seed, rate=rate)
         summary, _ = serve(trace, args.precision, budget, args.slots, args.k, realtime=True,
-                           layout=args.layout)
+                           layout=args.layout, streams=args.streams, cohort_bytes=cohort)
         summary["rate"] = rate
         if frac is not None:
             summary["fraction_of_capacity"] = frac

@@ -32,15 +32,18 @@ def _moments_after(batch, slots):
     return {s: batch.moments(s) for s in slots}
 
 
-@pytest.mark.parametrize("precision,cohort", [("fp32", 0), ("fp16", 0), ("fp32", 1 << 20),
-                                              ("fp16", 3 << 20)])
-def test_alone_equals_in_mix(precision, cohort):
+@pytest.mark.parametrize("precision,cohort,streams", [
+    ("fp32", 0, 2), ("fp16", 0, 2), ("fp32", 1 << 20, 1), ("fp32", 1 << 20, 2),
+    ("fp16", 3 << 20, 1), ("fp16", 3 << 20, 2)])
+def test_alone_equals_in_mix(precision, cohort, streams):
     """cohort = 0 puts every jet in one launch; a small cohort limit splits
-    them into several cache-sized cohorts run one after another."""
+    them into several cache-sized cohorts, run one after another on one
+    stream or two at a time on two."""
     from paper_1002_3028_amd import lbm
     jets = _jets()
     with lbm.Batch(1 << 30, 16, precision) as mix:
         mix.set_cohort_bytes(cohort)
+        mix.set_streams(streams)
         slots = [mix.admit(p, inlet, steps) for p, inlet, steps in jets]
         for _ in range(12):
             mix.run(10)
@@ -94,6 +97,7 @@ def test_continuous_admission_and_retire():
             alone.run(steps)
             refs.append(alone.moments(s))
     with lbm.Batch(1 << 30, 3, "fp32") as b:
+        b.set_cohort_bytes(1 << 20)  # several cohorts, on the default two streams
         pending = list(range(len(jets)))
         live = {}
         done = {}
@@ -119,6 +123,17 @@ def test_continuous_admission_and_retire():
     for q in range(len(jets)):
         for key in refs[q]:
             assert np.array_equal(done[q][key], refs[q][key]), (q, key)
+
+
+def test_stream_count_validated():
+    from paper_1002_3028_amd import lbm
+    with lbm.Batch(1 << 24, 2, "fp32") as b:
+        for n in (0, 3, -1):
+            with pytest.raises(lbm.LbmError) as e:
+                b.set_streams(n)
+            assert e.value.code == lbm.EINVAL
+        b.set_streams(1)
+        b.set_streams(2)
 
 
 def test_budget_admission():
