@@ -172,11 +172,13 @@ int lbm_probe_copy(void *dst, const void *src, size_t bytes, void *hip_stream);
  * A batch owns up to max_slots resident jets whose population buffers are
  * carved out of budget_bytes of device memory.  lbm_batch_run advances every
  * active jet by up to k steps: the active jets are grouped into cohorts of
- * at most cohort_bytes of buffers (default 200 MiB, so that a cohort stays in
- * the Infinity Cache), and each cohort gets k steps of one persistent launch
- * per step over all its jets (HIP graphs), cohort after cohort.  A jet stops
- * at its own target step count.  Each jet's result is bitwise the same as
- * that of the same jet run alone.  Precision is common to the batch. */
+ * at most cohort_bytes of buffers (default 112 MiB, so that the two cohorts
+ * in flight at once stay in the Infinity Cache), and each cohort gets k
+ * steps of one persistent launch per step over all its jets (HIP graphs),
+ * cohorts alternating between two streams (lbm_batch_set_streams).  A jet
+ * stops at its own target step count.  Each jet's result is bitwise the
+ * same as that of the same jet run alone.  Precision is common to the
+ * batch. */
 typedef struct lbm_batch lbm_batch;
 int lbm_batch_create(size_t budget_bytes, int32_t max_slots, int32_t precision,
                      void *hip_stream, lbm_batch **out);
