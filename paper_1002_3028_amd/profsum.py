@@ -72,8 +72,10 @@ def traffic(args):
     f_copy = statistics.median(pick(fetch, "copy_kernel")) * 1024
     w_copy = statistics.median(pick(write, "copy_kernel")) * 1024
     f_factor, w_factor = f_copy / copy_bytes, w_copy / copy_bytes
-    f_k = statistics.median(pick(fetch, args.kernel)) * 1024 / f_factor
-    w_k = statistics.median(pick(write, args.kernel)) * 1024 / w_factor
+    # launches of unequal size (the cohorts of a batch) take the mean
+    avg = statistics.mean if args.mean else statistics.median
+    f_k = avg(pick(fetch, args.kernel)) * 1024 / f_factor
+    w_k = avg(pick(write, args.kernel)) * 1024 / w_factor
     alg = args.bytes_per_node * args.nodes
     lines = [
         f"# HBM traffic per launch of {args.kernel} ({args.title})",
@@ -109,6 +111,8 @@ def main():
     b.add_argument("--kernel", required=True, help="substring of the kernel name")
     b.add_argument("--copy-mib", type=int, default=256)
     b.add_argument("--nodes", type=int, required=True)
+    b.add_argument("--mean", action="store_true",
+                   help="mean over launches (default: median)")
     b.add_argument("--bytes-per-node", type=int, required=True)
     b.add_argument("--out", required=True)
     b.add_argument("--title", required=True)
