@@ -215,13 +215,14 @@ int lbm_batch_set_launch(lbm_batch *b, int32_t tile_shape, int32_t workgroups);
  * default 112 MiB, so that the two cohorts running at once fit the 256 MB
  * Infinity Cache). */
 int lbm_batch_set_cohort_bytes(lbm_batch *b, size_t bytes);
-/* Streams the cohorts of a run are spread over: 1 (the batch's stream) or 2
- * (the default: odd cohorts on a second stream of default priority that the
- * library creates; it starts after the work already queued on the batch's
- * stream, and later work on the batch's stream waits for it, so callers see
- * one stream).  Results are the same bits either way.  Synchronises;
- * LBM_EINVAL for other values, LBM_EDEVICE (and one stream) if the second
- * stream cannot be created. */
+/* Streams the cohorts of a run are spread over, 1 to 4: cohort c runs on
+ * stream c mod n, stream 0 being the batch's stream and the others streams
+ * of default priority that the library creates.  They start after the work
+ * already queued on the batch's stream, and later work on the batch's stream
+ * waits for them, so callers see one stream.  Default 2 (measured best with
+ * the default cohorts; 3 or 4 smaller cohorts were slower).  Results are the
+ * same bits for any n.  Synchronises; LBM_EINVAL for other values,
+ * LBM_EDEVICE (and one stream) if a stream cannot be created. */
 int lbm_batch_set_streams(lbm_batch *b, int32_t n);
 void lbm_batch_destroy(lbm_batch *b);
 

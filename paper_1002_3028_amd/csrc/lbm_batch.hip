@@ -98,9 +98,11 @@ struct lbm_batch {
   std::map<std::tuple<int, int, int, int>, hipGraphExec_t> graphs;  // (k, shape, grid, cohort)
   // cohorts alternate between the batch's stream and a second one, so that
   // one cohort's launches fill the device while the other's start or drain
+  static constexpr int MAX_STREAMS = 4;
   int32_t nstreams = 2;
-  hipStream_t side = nullptr;
-  hipEvent_t fork = nullptr, join = nullptr;
+  hipStream_t side[MAX_STREAMS - 1] = {};  // streams 1.. (stream 0 is `stream`)
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[MAX_STREAMS - 1] = {};
 };
 
 namespace {
@@ -386,18 +388,18 @@ int lbm_batch_run(lbm_batch *b, int32_t k_steps) {
   int rc;
   if (b->dirty && (rc = rebuild(b))) return rc;
   if (b->active.empty()) return LBM_OK;
-  const bool two = b->nstreams == 2 && b->n_cohorts > 1;
-  if (two) {
-    // the second stream starts after everything queued so far
+  const int32_t ns = std::max(1, std::min(b->nstreams, b->n_cohorts));
+  if (ns > 1) {
+    // the other streams start after everything queued so far
     LBM_HIP(hipEventRecord(b->fork, b->stream));
-    LBM_HIP(hipStreamWaitEvent(b->side, b->fork, 0));
+    for (int32_t q = 0; q + 1 < ns; ++q) LBM_HIP(hipStreamWaitEvent(b->side[q], b->fork, 0));
   }
   for (int32_t c = 0; c < b->n_cohorts; ++c)
-    if ((rc = run_group(b, k_steps, c, two && (c & 1) ? b->side : b->stream))) return rc;
-  if (two) {
-    // and everything queued later on the batch's stream waits for it
-    LBM_HIP(hipEventRecord(b->join, b->side));
-    LBM_HIP(hipStreamWaitEvent(b->stream, b->join, 0));
+    if ((rc = run_group(b, k_steps, c, c % ns ? b->side[c % ns - 1] : b->stream))) return rc;
+  // and everything queued later on the batch's stream waits for them
+  for (int32_t q = 0; q + 1 < ns; ++q) {
+    LBM_HIP(hipEventRecord(b->join[q], b->side[q]));
+    LBM_HIP(hipStreamWaitEvent(b->stream, b->join[q], 0));
   }
   // mirror of the advance kernel: every pair a jet took in full toggled its flip
   int nsh;
@@ -529,22 +531,20 @@ int lbm_batch_set_launch(lbm_batch *b, int32_t tile_shape, int32_t workgroups) {
 }
 
 int lbm_batch_set_streams(lbm_batch *b, int32_t n) {
-  if (!b || (n != 1 && n != 2)) return LBM_EINVAL;
+  if (!b || n < 1 || n > lbm_batch::MAX_STREAMS) return LBM_EINVAL;
   LBM_HIP(hipStreamSynchronize(b->stream));
-  if (b->side) LBM_HIP(hipStreamSynchronize(b->side));
-  if (n == 2 && !b->side) {
-    const bool ok = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) == hipSuccess &&
-                    hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) == hipSuccess &&
-                    hipEventCreateWithFlags(&b->join, hipEventDisableTiming) == hipSuccess;
-    if (!ok) {
-      if (b->fork) (void)hipEventDestroy(b->fork);
-      if (b->join) (void)hipEventDestroy(b->join);
-      if (b->side) (void)hipStreamDestroy(b->side);
-      b->fork = b->join = nullptr;
-      b->side = nullptr;
-      b->nstreams = 1;
-      return LBM_EDEVICE;
-    }
+  for (hipStream_t s : b->side)
+    if (s) LBM_HIP(hipStreamSynchronize(s));
+  bool ok = b->fork || hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) == hipSuccess;
+  for (int32_t q = 0; ok && q + 1 < n; ++q) {
+    if (!b->side[q] && hipStreamCreateWithFlags(&b->side[q], hipStreamNonBlocking) != hipSuccess)
+      b->side[q] = nullptr, ok = false;
+    if (ok && !b->join[q] && hipEventCreateWithFlags(&b->join[q], hipEventDisableTiming) != hipSuccess)
+      b->join[q] = nullptr, ok = false;
+  }
+  if (!ok) {
+    b->nstreams = 1;
+    return LBM_EDEVICE;
   }
   b->nstreams = n;
   return LBM_OK;
@@ -553,7 +553,8 @@ int lbm_batch_set_streams(lbm_batch *b, int32_t n) {
 void lbm_batch_destroy(lbm_batch *b) {
   if (!b) return;
   if (b->stream) (void)hipStreamSynchronize(b->stream);
-  if (b->side) (void)hipStreamSynchronize(b->side);
+  for (hipStream_t st : b->side)
+    if (st) (void)hipStreamSynchronize(st);
   drop_graphs(b);
   for (Slot &s : b->slots) {
     if (s.d_table) (void)hipFree(s.d_table);
@@ -568,8 +569,10 @@ void lbm_batch_destroy(lbm_batch *b) {
   if (b->d_flags) (void)hipFree(b->d_flags);
   if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
   if (b->fork) (void)hipEventDestroy(b->fork);
-  if (b->join) (void)hipEventDestroy(b->join);
-  if (b->side) (void)hipStreamDestroy(b->side);
+  for (int q = 0; q + 1 < lbm_batch::MAX_STREAMS; ++q) {
+    if (b->join[q]) (void)hipEventDestroy(b->join[q]);
+    if (b->side[q]) (void)hipStreamDestroy(b->side[q]);
+  }
   delete b;
 }
 

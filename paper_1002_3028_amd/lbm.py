@@ -443,7 +443,7 @@ class Batch:
         _check(self.lib.lbm_batch_set_cohort_bytes(self.b, int(nbytes)), "lbm_batch_set_cohort_bytes")
 
     def set_streams(self, n: int):
-        """Spread each run's cohorts over 1 or 2 streams."""
+        """Spread each run's cohorts over 1 to 4 streams (default 2)."""
         _check(self.lib.lbm_batch_set_streams(self.b, int(n)), "lbm_batch_set_streams")
 
     def set_launch(self, tile_shape: int = -1, workgroups: int = 0):

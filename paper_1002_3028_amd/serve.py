@@ -41,7 +41,7 @@ def serve(requests, precision: str = "fp16", budget_bytes: int = 16 << 30,
     so a budget holds twice as many jets.
 
     realtime=False admits every request at t = 0 (saturation: measures the
-    capacity).  streams (1 or 2) and cohort_bytes override the batch's
+    capacity).  streams (1 to 4) and cohort_bytes override the batch's
     defaults when given.  Returns a summary dict, plus per-request records.
     """
     order = sorted(range(len(requests)), key=lambda q: requests[q][0])
@@ -125,7 +125,7 @@ def main():
     ap.add_argument("--k", type=int, default=50)
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--layout", choices=["two", "single"], default="two")
-    ap.add_argument("--streams", type=int, default=0, help="1 or 2 (0: the batch's default)")
+    ap.add_argument("--streams", type=int, default=0, help="1 to 4 (0: the batch's default)")
     ap.add_argument("--cohort-mib", type=int, default=-1,
                     help="cohort limit in MiB (-1: the batch's default, 0: one cohort)")
     ap.add_argument("--sweep", default="",

@@ -34,7 +34,7 @@ def _moments_after(batch, slots):
 
 @pytest.mark.parametrize("precision,cohort,streams", [
     ("fp32", 0, 2), ("fp16", 0, 2), ("fp32", 1 << 20, 1), ("fp32", 1 << 20, 2),
-    ("fp16", 3 << 20, 1), ("fp16", 3 << 20, 2)])
+    ("fp32", 1 << 20, 3), ("fp16", 3 << 20, 1), ("fp16", 3 << 20, 2), ("fp16", 1 << 20, 4)])
 def test_alone_equals_in_mix(precision, cohort, streams):
     """cohort = 0 puts every jet in one launch; a small cohort limit splits
     them into several cache-sized cohorts, run one after another on one
@@ -128,12 +128,12 @@ def test_continuous_admission_and_retire():
 def test_stream_count_validated():
     from paper_1002_3028_amd import lbm
     with lbm.Batch(1 << 24, 2, "fp32") as b:
-        for n in (0, 3, -1):
+        for n in (0, 5, -1):
             with pytest.raises(lbm.LbmError) as e:
                 b.set_streams(n)
             assert e.value.code == lbm.EINVAL
-        b.set_streams(1)
-        b.set_streams(2)
+        for n in (1, 4, 2):
+            b.set_streams(n)
 
 
 def test_budget_admission():
