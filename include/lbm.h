@@ -206,10 +206,9 @@ int lbm_batch_sync(lbm_batch *b);
 /* Bytes a jet of this configuration takes from the budget. */
 int lbm_batch_jet_bytes(const lbm_batch *b, const lbm_config *cfg, size_t *bytes);
 int lbm_batch_active(const lbm_batch *b, int32_t *n_active, size_t *bytes_used);
-/* Tile shape of the step kernel (index into the compiled shapes; -1 = auto;
- * a two-step shape is used only while no active jet has periodic edges) and
- * the number of persistent workgroups (0 = auto: as many as the device holds
- * at once for that kernel). */
+/* Tile shape of the step kernel (index into the compiled shapes; -1 = auto)
+ * and the number of persistent workgroups (0 = auto: as many as the device
+ * holds at once for that kernel). */
 int lbm_batch_set_launch(lbm_batch *b, int32_t tile_shape, int32_t workgroups);
 /* Cohort size limit in bytes of population buffers (0: all jets together;
  * default 112 MiB, so that the two cohorts running at once fit the 256 MB
@@ -237,13 +236,12 @@ int lbm_tile_shape(int32_t index, int32_t *bx, int32_t *by, int32_t *ny, int32_t
  * workgroup); n <= 8 entries are written.
  * Shapes with 2 steps per launch run two time steps of eq. (1) per kernel
  * launch on an LDS-resident 64 x (by * ny) tile with a one-node frame,
- * bit-identical to two one-step launches; they reject jets with periodic
- * edges (lbm_set_tile_shape returns LBM_EINVAL; a batch holding such a jet
- * falls back to the default shape). */
+ * bit-identical to two one-step launches, on every edge rule (with periodic
+ * x edges the frame wraps to the other end of the domain). */
 int lbm_tile_shape_info(int32_t index, int32_t *info, int32_t n);
 /* Select the launch variant of a handle (synchronises; EINVAL for an unknown
- * index, a two-step shape on a periodic configuration, or any shape but 0 on
- * a single-buffer handle, whose in-place kernel uses shape 0's tiles). */
+ * index, or any shape but 0 on a single-buffer handle, whose in-place kernel
+ * uses shape 0's tiles). */
 int lbm_set_tile_shape(lbm_handle *h, int32_t index);
 
 #ifdef __cplusplus

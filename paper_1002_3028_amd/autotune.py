@@ -65,7 +65,7 @@ def time_shapes(params: dict, inlet, precision: str, steps: int = 200, warmup: i
         for q in (range(len(lbm.tile_shapes())) if shapes is None else shapes):
             try:
                 s.set_tile_shape(q)
-            except lbm.LbmError as e:  # two-step shapes refuse periodic jets
+            except lbm.LbmError as e:  # a shape this handle cannot take
                 if e.code != lbm.EINVAL:
                     raise
                 continue

@@ -59,7 +59,6 @@ int set_shape(lbm_handle *h, int shape) {
   int n;
   const TileShape *ts = tile_shapes(&n);
   if (shape < 0 || shape >= n) return LBM_EINVAL;
-  if (ts[shape].steps == 2 && has_periodic(&h->cfg)) return LBM_EINVAL;
   if (h->layout == LBM_LAYOUT_SINGLE && shape != 0) return LBM_EINVAL;
   int32_t tx;
   h->ntiles = tiles_of(&h->cfg, shape, &tx);
@@ -204,9 +203,7 @@ int create_common(const lbm_config *cfg, void *dev_buf, size_t bytes, void *stre
   std::vector<float4> rows;
   make_inlet(&h->cfg, 0, nullptr, nullptr, nullptr, rows);
   if ((rc = upload_inlet(h, rows, 1)) ||
-      (rc = set_shape(h, h->layout == LBM_LAYOUT_SINGLE
-                             ? 0
-                             : default_tile_shape(h->prec, has_periodic(&h->cfg))))) {
+      (rc = set_shape(h, h->layout == LBM_LAYOUT_SINGLE ? 0 : default_tile_shape(h->prec)))) {
     release(h);
     return rc;
   }

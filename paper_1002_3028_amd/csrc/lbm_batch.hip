@@ -107,17 +107,10 @@ struct lbm_batch {
 
 namespace {
 
-// The requested (or default) shape, unless it is a two-step shape and an
-// active jet has periodic edges: then the one-step default.
+// The requested (or default) shape.
 int pick_shape(const lbm_batch *b) {
   if (b->layout == LBM_LAYOUT_SINGLE) return 0;  // the in-place kernel's tiles
-  const int s = b->shape >= 0 ? b->shape : default_tile_shape(b->prec, false);
-  int n;
-  if (tile_shapes(&n)[s].steps == 2)
-    for (const Slot &sl : b->slots)
-      if (sl.used && sl.step < sl.target && has_periodic(&sl.cfg))
-        return default_tile_shape(b->prec, true);
-  return s;
+  return b->shape >= 0 ? b->shape : default_tile_shape(b->prec);
 }
 
 void drop_graphs(lbm_batch *b) {

@@ -159,9 +159,9 @@ const TileShape *tile_shapes(int *count) {
 // FP32 storage: the two-step kernel on 64 x 8 tiles with f_0 kept in
 // registers (12-plane image, 5 workgroups per CU): the HBM traffic per step
 // halves and the arithmetic still fits under it.  16-bit storage, whose step
-// is arithmetic-limited already, and periodic jets: one step per launch.
-int default_tile_shape(int prec, bool periodic) {
-  if (prec != LBM_PREC_FP32 || periodic) return 0;
+// is arithmetic-limited already: one step per launch.
+int default_tile_shape(int prec) {
+  if (prec != LBM_PREC_FP32) return 0;
   int n;
   const TileShape *s = tile_shapes(&n);
   for (int q = 0; q < n; ++q)

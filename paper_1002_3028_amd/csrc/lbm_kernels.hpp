@@ -256,11 +256,14 @@ template <class C, int EH, int P0>
 struct LdsImage {
   float *s;
   int ia, ja;
+  int wrap;  // nx for periodic x edges (a column nx away is the same column), else 0
   __device__ __forceinline__ void set(const JetDesc &d, int p, int x, int y, float v) const {
     if (p >= P0) s[((p - P0) * EH + y) * PAIR_W + x] = storage_round<C>(d, p, v);
   }
   __device__ __forceinline__ void put(const JetDesc &d, int p, int i, int j, float v) const {
-    const int x = i - ia + 1, y = j - ja + 1;
+    int x = i - ia + 1;
+    const int y = j - ja + 1;
+    if (wrap) x += x < 0 ? wrap : (x >= PAIR_W ? -wrap : 0);
     if (((unsigned)x < (unsigned)PAIR_W) & ((unsigned)y < (unsigned)EH)) set(d, p, x, y, v);
   }
 };
@@ -283,9 +286,9 @@ struct LdsImage {
 // assigns to the odd step count, so each full pair toggles the jet's flip:
 // the advance kernel applies it, `tog` accounts for the pairs issued since.
 // A jet one step short of its target (or nsteps == 1) takes one step.
-// Periodic edges are not handled (their ghost values come from the far end
-// of the domain, outside the frame); the runtimes do not select this kernel
-// for such jets.
+// With periodic x edges the frame columns beyond the domain are computed as
+// the nodes at its other end, and the epilogue's ghost writes are wrapped into
+// the image the same way, so the tile sees what the ghost ring would hold.
 // ---------------------------------------------------------------------------
 template <class C, int TY, int NW, int W, int CP>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(W, 8))) void pair_kernel(
@@ -355,7 +358,16 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(W, 8)))
         }
       }
     } else {
-      const LdsImage<C, EH, P0> im{img, ia, ja};
+      // Periodic x edges: the frame columns beyond the domain are the
+      // columns at its other end, computed in step 1 like any other node
+      // (their values, and the ghost values their epilogue writes, are those
+      // of the same nodes at the other end, so duplicates agree).
+      const bool px = d.bc[0] == BC_PERIODIC;
+      // (frame columns lie in -1 .. ia + 64; more than one turn only when nx < 65)
+      const auto wrap_i = [&](int i) {
+        return i < 0 ? i + nx : (i < nx ? i : (i - nx < nx ? i - nx : i % nx));
+      };
+      const LdsImage<C, EH, P0> im{img, ia, ja, px ? nx : 0};
       // Constant ghosts (equilibrium sides) are never rewritten by the
       // epilogue: copy the ring positions of the image from the source
       // buffer first.  Every other ghost value the tile pulls is produced in
@@ -366,9 +378,11 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(W, 8)))
         const Src<C> src{as_global(static_cast<const T *>(src_raw)), d.plane, d.pitch};
         for (int n = lane + 64 * wave; n < EH * PAIR_W; n += 64 * NW) {
           const int y = n / PAIR_W, x = n - y * PAIR_W;
-          const int i = ia - 1 + x, j = ja - 1 + y;
+          const int j = ja - 1 + y;
+          // with periodic x only the rows j = -1, nr are ring (any column, wrapped)
+          const int i = px ? wrap_i(ia - 1 + x) : ia - 1 + x;
           const bool ring = (i >= -1) & (i <= nx) & (j >= -1) & (j <= nr) &
-                            ((i == -1) | (i == nx) | (j == -1) | (j == nr));
+                            ((!px & ((i == -1) | (i == nx))) | (j == -1) | (j == nr));
           if (ring) {
             float v[NPOP];
 #pragma unroll
@@ -397,7 +411,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(W, 8)))
       const auto task_voff = [&](int q) {
         int x, y;
         task_xy(q, x, y);
-        const int i = min(max(ia - 1 + x, 0), nx - 1);
+        const int i = px ? wrap_i(ia - 1 + x) : min(max(ia - 1 + x, 0), nx - 1);
         const int j = min(max(ja - 1 + min(y, EH - 1), 0), nr - 1);
         return (uint32_t)node_index(d.pitch, i, j) * ES;
       };
@@ -418,7 +432,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(W, 8)))
           };
           int x, y;
           task_xy(q, x, y);
-          const int i = ia - 1 + x, j = ja - 1 + y;
+          const int i = px ? wrap_i(ia - 1 + x) : ia - 1 + x, j = ja - 1 + y;
           float f[9], g[4];
           decode_raw<C>(d, raw[k & 1], f, g);
           const float rr = d.r0 + (float)min(max(j, 0), nr - 1) + 0.5f;

@@ -53,19 +53,15 @@ int make_inlet(const lbm_config *c, int32_t n_t, const double *ux, const double 
 // ---- kernel tables ---------------------------------------------------------
 // A launch variant: block (bx, by), tile (bx * nx) x (by * ny) nodes, the
 // occupancy target, the cache policy, and the steps one launch advances
-// (2: the LDS-blocked two-step kernel, not valid for periodic jets).
+// (2: the LDS-blocked two-step kernel).
 struct TileShape {
   int bx, by, ny, nx, waves, cache, steps, lds;
   const void *fn[3];  // FP32, FP16-dev, BF16-dev
 };
 const TileShape *tile_shapes(int *count);
-int default_tile_shape(int prec, bool periodic);
+int default_tile_shape(int prec);
 
 inline int codec_index(int prec) { return prec - LBM_PREC_FP32; }
-
-inline bool has_periodic(const lbm_config *c) {
-  return c->bc[0] == BC_PERIODIC || c->bc[1] == BC_PERIODIC;
-}
 
 // One launch of tile shape `shape`: the step (or pair) at step0 + koff, with
 // `tog` the parity of two-step launches since the last advance and nsteps

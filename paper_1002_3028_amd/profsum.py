@@ -4,6 +4,9 @@
   traffic: HBM bytes per launch of one kernel from two --pmc runs
            (FETCH_SIZE, WRITE_SIZE), each scaled by what the same counter
            reads for the probe's copy of known size.
+  valu:    vector-ALU instructions executed per node update from a --pmc
+           run of SQ_INSTS_VALU and SQ_WAVES (one instruction of a wave
+           serves 64 lanes, so per update = total / (updates / 64)).
 
 Both write a short text file that records the command which produced the
 counters and, for traffic, the SHA-256 of the kernel sources it was taken on.
@@ -96,6 +99,30 @@ def traffic(args):
     print("\n".join(lines))
 
 
+def valu(args):
+    insts = [x for k, v in _per_kernel(args.csv, "SQ_INSTS_VALU").items() if args.kernel in k
+             for x in v]
+    waves = [x for k, v in _per_kernel(args.csv, "SQ_WAVES").items() if args.kernel in k
+             for x in v]
+    if not insts or not waves:
+        raise SystemExit(f"no SQ_INSTS_VALU / SQ_WAVES for a kernel matching {args.kernel!r}")
+    per_launch = statistics.median(insts)
+    lines = [
+        f"# vector-ALU instructions of {args.kernel} ({args.title})",
+        f"# command: {args.command}",
+        f"launches: {len(insts)}",
+        f"valu_instructions_per_launch: {per_launch:.0f}",
+        f"waves_per_launch: {statistics.median(waves):.0f}",
+        f"valu_per_wave: {per_launch / statistics.median(waves):.1f}",
+        f"node_updates_per_launch: {args.updates}",
+        f"valu_per_node_update: {per_launch / (args.updates / 64):.1f}",
+        f"kernel_source_sha256: {kernel_source_sha256()}",
+    ]
+    with open(args.out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -118,8 +145,15 @@ def main():
     b.add_argument("--title", required=True)
     b.add_argument("--command-fetch", required=True)
     b.add_argument("--command-write", required=True)
+    c = sub.add_parser("valu")
+    c.add_argument("--csv", required=True)
+    c.add_argument("--kernel", required=True, help="substring of the kernel name")
+    c.add_argument("--updates", type=int, required=True, help="node updates per launch")
+    c.add_argument("--out", required=True)
+    c.add_argument("--title", required=True)
+    c.add_argument("--command", required=True)
     args = ap.parse_args()
-    stats(args) if args.cmd == "stats" else traffic(args)
+    {"stats": stats, "traffic": traffic, "valu": valu}[args.cmd](args)
 
 
 if __name__ == "__main__":

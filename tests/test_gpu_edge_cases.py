@@ -22,15 +22,11 @@ def _gpu():
 
 
 def _kernels(p):
-    """(kwargs of lbm.Solver) for the three kernels; two steps per launch
-    only without periodic edges."""
+    """(kwargs of lbm.Solver) for the three kernels."""
     from paper_1002_3028_amd import lbm
     infos = lbm.tile_shape_infos()
     pair = [q for q, i in enumerate(infos) if i["steps"] == 2 and i["cache"] == 8][0]
-    out = [dict(tile_shape=0), dict(layout="single")]
-    if "periodic" not in p["bc"]:
-        out.append(dict(tile_shape=pair, graph_steps=4))
-    return out
+    return [dict(tile_shape=0), dict(layout="single"), dict(tile_shape=pair, graph_steps=4)]
 
 
 def _compare(p, inlet, steps, tol):

@@ -2,24 +2,24 @@
 
 The intermediate state is rounded through the storage codec, so a pair of
 steps must give exactly the bits of two one-step launches (shape 0): on every
-non-periodic edge rule and corner, in every precision, on grids with ragged
-tiles in both directions and grids smaller than one tile, for odd step
-counts (a final single step), with and without graphs, in a batch whose jets
-stop mid-pair, and across a checkpoint taken after an odd number of steps.
-Periodic jets are refused by a single-jet handle and make a batch fall back
-to the one-step kernel.  The pair path is also compared with the FP64 oracle
-directly, at the one-step kernel's tolerance.
+edge rule and corner (periodic x edges included: the frame wraps to the other
+end of the domain, more than once on grids narrower than the frame), in every
+precision, on grids with ragged tiles in both directions and grids smaller
+than one tile, for odd step counts (a final single step), with and without
+graphs, in a batch whose jets stop mid-pair, and across a checkpoint taken
+after an odd number of steps.  The pair path is also compared with the FP64
+oracle directly, at the one-step kernel's tolerance.
 """
 import numpy as np
 import pytest
 
-from gpu_common import host_threads, noisy_inlet, rel_err, require_gpu, tiny_params
+from gpu_common import CASES, host_threads, noisy_inlet, rel_err, require_gpu, tiny_params
 
 pytestmark = pytest.mark.gpu
 
-NONPERIODIC = ["jet", "eq", "xwalls", "substrate", "slab"]
-# (nx, nr): ragged in x and r; narrower and lower than one tile; exact tiles
-GRIDS = [(200, 45), (40, 5), (128, 24), (65, 13)]
+# (nx, nr): ragged in x and r; narrower and lower than one tile; exact tiles;
+# narrower than a third of the frame (a periodic frame wraps more than once)
+GRIDS = [(200, 45), (40, 5), (128, 24), (65, 13), (20, 9)]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -72,7 +72,7 @@ def test_pair_shapes_compiled():
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp16", "bf16"])
-@pytest.mark.parametrize("case", NONPERIODIC)
+@pytest.mark.parametrize("case", CASES)
 def test_pair_equals_single(case, precision):
     for nx, nr in GRIDS:
         p = tiny_params(nx, nr, case, (nx + nr) % 2)
@@ -150,20 +150,11 @@ def test_switch_shapes_mid_run():
     assert np.array_equal(got[0], ref[0]) and np.array_equal(got[1], ref[1])
 
 
-def test_periodic_refused_by_single_jet():
-    from paper_1002_3028_amd import lbm
-    p = tiny_params(64, 16, "closed", 1)
-    for q in _pair_shapes():
-        with pytest.raises(lbm.LbmError) as e:
-            lbm.Solver(p, "fp32", tile_shape=q)
-        assert e.value.code == lbm.EINVAL
-
-
 @pytest.mark.parametrize("precision", ["fp32", "fp16"])
 def test_batch_pairs_with_uneven_targets(precision):
     """Jets with odd and even targets, advanced in groups of 10 and 7 steps
-    with a two-step shape: each jet equals itself alone (one-step kernel);
-    a periodic jet admitted later makes the batch fall back, still exact."""
+    with a two-step shape: each jet equals itself alone (one-step kernel),
+    a periodic jet admitted later included."""
     from paper_1002_3028_amd import lbm
     jets = []
     for q, (nx, nr, case, steps) in enumerate([(200, 45, "jet", 61), (64, 16, "xwalls", 62),
@@ -185,7 +176,7 @@ def test_batch_pairs_with_uneven_targets(precision):
             slots = [b.admit(p, inlet, steps) for p, inlet, steps in jets[:4]]
             for _ in range(4):
                 b.run(10)
-            late = b.admit(*jets[4])  # periodic: the rest runs one step per launch
+            late = b.admit(*jets[4])  # periodic
             for _ in range(8):
                 b.run(7)
             got = [b.moments(s) for s in slots + [late]]
