@@ -31,9 +31,10 @@ BYTES_PER_NODE = {"fp32": 104, "fp16": 52, "bf16": 52}
 # Vector ALU issue: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz (a wave64 FP32
 # instruction every 4 cycles per SIMD; packed FP32 not used), lane-ops/s.
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
-# VALU instructions of one FP32 node update: the one-step kernel's hot path
-# (loads to stores) as compiled for gfx950.
-VALU_PER_UPDATE = 185
+# VALU instructions in the collision of one FP32 node update as compiled for
+# gfx950 (eqs. 2-6 and 1 from the pulled values to the relaxed ones; the
+# counters' executed figure per kernel is read from profiles/valu_*.txt).
+VALU_COLLISION = 185
 
 
 def _ensure_built():
@@ -47,9 +48,9 @@ def kernel_of(info):
     return "pair_kernel" if info["steps"] == 2 else "step_kernel"
 
 
-def read_traffic(name):
-    """Per-launch HBM bytes (read + write) from a committed counter summary,
-    or None when absent or taken on another version of the kernel source."""
+def read_summary(name, key):
+    """A value from a committed counter summary under profiles/, or None when
+    absent or taken on another version of the kernel source."""
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
@@ -62,9 +63,30 @@ def read_traffic(name):
     if vals.get("kernel_source_sha256") != kernel_source_sha256():
         return None
     try:
-        return float(vals["hbm_bytes_per_launch"])
+        return float(vals[key])
     except (KeyError, ValueError):
         return None
+
+
+def read_traffic(name):
+    """Per-launch HBM bytes (read + write) from a committed counter summary."""
+    return read_summary(name, "hbm_bytes_per_launch")
+
+
+def alu_roofline(kernel, nodes, ms_step):
+    """The launch against vector-ALU issue: VALU instructions executed per
+    node update (SQ_INSTS_VALU over SQ_WAVES from the committed counter
+    summary of this kernel; null when stale) x node updates per second, and
+    the collision's own instruction count beside it."""
+    kind = kernel.split("_")[0]
+    executed = read_summary(f"valu_{kind}_fp32_2048x512.txt", "valu_per_node_update")
+    out = {"unit": "T lane-op/s", "peak": round(VALU_PEAK_TOPS, 2),
+           "valu_collision_per_node_update": VALU_COLLISION,
+           "valu_executed_per_node_update": executed, "achieved": None, "frac": None}
+    if executed:
+        achieved = executed * nodes / (ms_step * 1e-3) / 1e12
+        out.update(achieved=round(achieved, 2), frac=round(achieved / VALU_PEAK_TOPS, 4))
+    return out
 
 
 def time_jet(params, inlet, precision, steps, warmup, graph_steps=50, check_every=1000,
@@ -309,11 +331,7 @@ def main():
                      "kernel_ms_per_launch": round(ms_launch, 5),
                      "dram_GBps": (round(traffic / (ms_launch * 1e-3) / 1e9, 1)
                                    if traffic else None),
-                     "alu": {"unit": "T lane-op/s", "peak": round(VALU_PEAK_TOPS, 2),
-                             "valu_per_node_update": VALU_PER_UPDATE,
-                             "achieved": round(VALU_PER_UPDATE * nodes / (ms_step * 1e-3) / 1e12, 2),
-                             "frac": round(VALU_PER_UPDATE * nodes / (ms_step * 1e-3) / 1e12 /
-                                           VALU_PEAK_TOPS, 4)}},
+                     "alu": alu_roofline(kernel_of(info), nodes, ms_step)},
     }
     if not args.no_extra:
         extra = {}
