@@ -1,0 +1,83 @@
+"""The counter summaries that bench.py reads: traffic and VALU figures from
+synthetic rocprofv3 CSVs, and the source check that turns a summary taken on
+other kernel sources into null."""
+import csv
+import os
+
+import pytest
+
+HEADER = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
+
+
+def _csv(path, rows):
+    with open(path, "w", newline="") as fh:
+        w = csv.writer(fh)
+        w.writerow(HEADER)
+        for q, (kernel, counter, value) in enumerate(rows):
+            w.writerow([q, kernel, counter, value])
+    return str(path)
+
+
+def _run(args):
+    import sys
+    from paper_1002_3028_amd import profsum
+    old = sys.argv
+    sys.argv = ["profsum"] + args
+    try:
+        profsum.main()
+    finally:
+        sys.argv = old
+
+
+def _vals(path):
+    out = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            out[k.strip()] = v.strip()
+    return out
+
+
+def test_traffic_scales_by_the_copy(tmp_path):
+    """FETCH reads half and WRITE all of a 256 MiB copy here: a kernel whose
+    counters read 50 and 100 KiB moves 100 + 100 KiB."""
+    mib = 256 * 1024  # KiB
+    fetch = _csv(tmp_path / "f.csv", [("copy_kernel(x)", "FETCH_SIZE", mib / 2),
+                                      ("pair_kernel<a>", "FETCH_SIZE", 50.0),
+                                      ("pair_kernel<a>", "FETCH_SIZE", 50.0)])
+    write = _csv(tmp_path / "w.csv", [("copy_kernel(x)", "WRITE_SIZE", mib),
+                                      ("pair_kernel<a>", "WRITE_SIZE", 100.0)])
+    out = tmp_path / "t.txt"
+    _run(["traffic", "--fetch", fetch, "--write", write, "--kernel", "pair_kernel",
+          "--nodes", "10", "--bytes-per-node", "40", "--out", str(out), "--title", "t",
+          "--command-fetch", "cf", "--command-write", "cw"])
+    v = _vals(out)
+    assert float(v["fetch_factor"]) == pytest.approx(0.5)
+    assert float(v["hbm_bytes_per_launch"]) == pytest.approx(200 * 1024)
+    assert float(v["traffic_over_algorithmic"]) == pytest.approx(200 * 1024 / 400, rel=1e-4)
+
+
+def test_valu_per_update(tmp_path):
+    """6400 instructions issued by the two waves that cover 128 node updates
+    (64 lanes each): 6400 / (128 / 64) = 3200 per node update."""
+    rows = [("step_kernel<b>", "SQ_INSTS_VALU", 6400.0), ("step_kernel<b>", "SQ_WAVES", 2.0)]
+    out = tmp_path / "v.txt"
+    _run(["valu", "--csv", _csv(tmp_path / "v.csv", rows), "--kernel", "step_kernel",
+          "--updates", "128", "--out", str(out), "--title", "t", "--command", "c"])
+    v = _vals(out)
+    assert float(v["valu_per_wave"]) == pytest.approx(3200.0)
+    assert float(v["valu_per_node_update"]) == pytest.approx(3200.0)
+
+
+def test_bench_reads_only_current_summaries(tmp_path, monkeypatch):
+    import bench
+    from paper_1002_3028_amd.profsum import kernel_source_sha256
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    (prof / "x.txt").write_text(f"hbm_bytes_per_launch: 123\nkernel_source_sha256: "
+                                f"{kernel_source_sha256()}\n")
+    (prof / "y.txt").write_text("hbm_bytes_per_launch: 456\nkernel_source_sha256: 0\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.read_traffic("x.txt") == 123.0
+    assert bench.read_traffic("y.txt") is None
+    assert bench.read_traffic("missing.txt") is None
