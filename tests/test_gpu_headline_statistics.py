@@ -1,0 +1,61 @@
+"""The 2048 x 512 jet itself (the benchmark's workload) against the FP64
+oracle through time-averaged profiles over steps [10 000, 20 000], sampled
+every 50 steps: centreline u_x(x), T(x) and radial u_x(r), T(r) at i = nx/2
+and i = nx-1, profile error ||d||_2 / ||ref||_2 per quantity within 1 %.
+
+The oracle needs about three minutes of 16 host cores for the 21 G node
+updates, so the test runs only when LBM_LONG_TESTS=1 is set; its result is
+recorded with the tolerances of the method."""
+import json
+import os
+import time
+
+import numpy as np
+import pytest
+
+from gpu_common import host_threads, require_gpu
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow,
+              pytest.mark.skipif(os.environ.get("LBM_LONG_TESTS") != "1",
+                                 reason="about 3 minutes of FP64 oracle; set LBM_LONG_TESTS=1")]
+
+N_STEPS, EVERY, CHUNK = 20000, 50, 1000
+
+
+def _sample(m):
+    nx = m["ux"].shape[1]
+    return {"ux": np.concatenate([m["ux"][0], m["ux"][:, nx // 2], m["ux"][:, -1]]),
+            "T": np.concatenate([m["T"][0], m["T"][:, nx // 2], m["T"][:, -1]])}
+
+
+def _averaged(solver, name):
+    t0 = time.time()
+    for q in range(N_STEPS // 2 // CHUNK):
+        solver.step(CHUNK)
+        print(f"{name}: step {(q + 1) * CHUNK}, {time.time() - t0:.0f} s", flush=True)
+    acc, n = {"ux": 0.0, "T": 0.0}, 0
+    for q in range(N_STEPS // 2 // EVERY + 1):
+        s = _sample(solver.moments())
+        acc = {k: acc[k] + s[k] for k in acc}
+        n += 1
+        if q < N_STEPS // 2 // EVERY:
+            solver.step(EVERY)
+        if q % (CHUNK // EVERY) == 0:
+            print(f"{name}: step {N_STEPS // 2 + q * EVERY}, {time.time() - t0:.0f} s", flush=True)
+    return {k: v / n for k, v in acc.items()}
+
+
+def test_headline_jet_time_averaged_profiles():
+    require_gpu()
+    import oracle
+    from paper_1002_3028_amd import inputs, lbm
+    p, inlet, _ = inputs.workload_single(n_t=N_STEPS)
+    with lbm.Solver(p, "fp32", graph_steps=EVERY) as s:
+        s.set_inlet(*inlet)
+        got = _averaged(s, "gpu")
+    with oracle.RefSolver(p, threads=host_threads()) as r:
+        r.set_inlet(*inlet)
+        ref = _averaged(r, "oracle")
+    err = {k: float(np.linalg.norm(got[k] - ref[k]) / np.linalg.norm(ref[k])) for k in ref}
+    print(json.dumps({"grid": "2048x512", "steps": N_STEPS, "profile_error": err}), flush=True)
+    assert err["ux"] < 1e-2 and err["T"] < 1e-2
