@@ -1,5 +1,6 @@
-"""The 2048 x 512 jet itself (the benchmark's workload) against the FP64
-oracle through time-averaged profiles over steps [10 000, 20 000], sampled
+"""The 2048 x 512 jet itself (the benchmark's workload), FP32 and FP16
+storage, against the FP64 oracle through time-averaged profiles over steps
+[10 000, 20 000], sampled
 every 50 steps: centreline u_x(x), T(x) and radial u_x(r), T(r) at i = nx/2
 and i = nx-1, profile error ||d||_2 / ||ref||_2 per quantity within 1 %.
 
@@ -45,17 +46,35 @@ def _averaged(solver, name):
     return {k: v / n for k, v in acc.items()}
 
 
-def test_headline_jet_time_averaged_profiles():
+@pytest.fixture(scope="module")
+def reference():
     require_gpu()
     import oracle
-    from paper_1002_3028_amd import inputs, lbm
+    from paper_1002_3028_amd import inputs
     p, inlet, _ = inputs.workload_single(n_t=N_STEPS)
-    with lbm.Solver(p, "fp32", graph_steps=EVERY) as s:
-        s.set_inlet(*inlet)
-        got = _averaged(s, "gpu")
     with oracle.RefSolver(p, threads=host_threads()) as r:
         r.set_inlet(*inlet)
         ref = _averaged(r, "oracle")
+    return p, inlet, ref
+
+
+@pytest.mark.parametrize("precision", [
+    "fp32",
+    # 16-bit storage rounds each population the same way step after step in
+    # the near-steady core; over 20 000 steps the time-averaged profiles move
+    # by 1.6e-2 (u_x) and 2.8e-2 (T), outside the 1 % budget (FP32: 2.9e-3,
+    # 1.9e-4).  Kept as an expected failure that reports its numbers.
+    pytest.param("fp16", marks=pytest.mark.xfail(
+        reason="FP16 storage drifts over 20 000 steps: 1.6e-2 u_x / 2.8e-2 T measured",
+        strict=False)),
+])
+def test_headline_jet_time_averaged_profiles(reference, precision):
+    from paper_1002_3028_amd import lbm
+    p, inlet, ref = reference
+    with lbm.Solver(p, precision, graph_steps=EVERY) as s:
+        s.set_inlet(*inlet)
+        got = _averaged(s, precision)
     err = {k: float(np.linalg.norm(got[k] - ref[k]) / np.linalg.norm(ref[k])) for k in ref}
-    print(json.dumps({"grid": "2048x512", "steps": N_STEPS, "profile_error": err}), flush=True)
+    print(json.dumps({"grid": "2048x512", "steps": N_STEPS, "precision": precision,
+                      "profile_error": err}), flush=True)
     assert err["ux"] < 1e-2 and err["T"] < 1e-2
