@@ -27,7 +27,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_NODE = {"fp32": 104, "fp16": 52, "bf16": 52}
+BYTES_PER_NODE = {"fp32": 104, "fp16": 52, "bf16": 52, "fp16sr": 52}
 # Vector ALU issue: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz (a wave64 FP32
 # instruction every 4 cycles per SIMD; packed FP32 not used), lane-ops/s.
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
@@ -348,14 +348,14 @@ def main():
         q1 = autotune.best_shape(p, inlet, "fp32", steps=1)
         w, ms, _ = time_jet(p, inlet, "fp32", steps_x, args.warmup // 2, tile_shape=q1)
         extra["fp32_2048x512_one_step"] = entry("fp32", q1, w, ms, nodes, steps_x)
-        for prec in ("fp16", "bf16"):
+        for prec in ("fp16", "bf16", "fp16sr"):
             q = autotune.best_shape(p, inlet, prec)
             w, ms, _ = time_jet(p, inlet, prec, steps_x, args.warmup // 2, tile_shape=q)
             extra[f"{prec}_2048x512"] = entry(prec, q, w, ms, nodes, steps_x)
         pl, inl, _ = inputs.workload_large(n_t=4000)
         nodes_l = pl["nx"] * pl["nr"]
         steps_l = max(100, args.steps // 10)
-        for prec in ("fp32", "fp16"):
+        for prec in ("fp32", "fp16", "fp16sr"):
             q = autotune.best_shape(pl, inl, prec)
             w, ms, _ = time_jet(pl, inl, prec, steps_l, 100, tile_shape=q)
             extra[f"{prec}_4096x1024"] = entry(prec, q, w, ms, nodes_l, steps_l)

@@ -61,7 +61,11 @@ enum lbm_status {
 enum lbm_precision {
   LBM_PREC_FP32 = 1,     /* 13 x 4 B per node                                */
   LBM_PREC_FP16DEV = 2,  /* binary16 of f_k - w_k rho_ref, g_k - g_ref/4     */
-  LBM_PREC_BF16DEV = 3   /* bfloat16 of the same deviations                  */
+  LBM_PREC_BF16DEV = 3,  /* bfloat16 of the same deviations                  */
+  LBM_PREC_FP16SR = 4    /* binary16 of the same deviations, rounded
+                            stochastically: up with the probability of the
+                            discarded fraction, the random number a hash of
+                            the value and the plane (reproducible)          */
 };
 
 /* Edge rules, per side: 0 = x0 (i = -1), 1 = x1 (i = nx), 2 = r0 (j = -1),

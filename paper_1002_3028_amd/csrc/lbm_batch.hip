@@ -229,7 +229,7 @@ int lbm_batch_create(size_t budget_bytes, int32_t max_slots, int32_t precision,
   *out = nullptr;
   if (max_slots < 1 || max_slots > 65536 || budget_bytes < 256) return LBM_EINVAL;
   if (precision != LBM_PREC_FP32 && precision != LBM_PREC_FP16DEV &&
-      precision != LBM_PREC_BF16DEV)
+      precision != LBM_PREC_BF16DEV && precision != LBM_PREC_FP16SR)
     return LBM_EINVAL;
   lbm_batch *b = new (std::nothrow) lbm_batch();
   if (!b) return LBM_ENOMEM;

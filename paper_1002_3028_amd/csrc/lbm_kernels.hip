@@ -54,7 +54,7 @@ int validate_config(const lbm_config *c, bool check_precision) {
     return LBM_EINVAL;
   if (check_precision) {
     if (c->precision != LBM_PREC_FP32 && c->precision != LBM_PREC_FP16DEV &&
-        c->precision != LBM_PREC_BF16DEV)
+        c->precision != LBM_PREC_BF16DEV && c->precision != LBM_PREC_FP16SR)
       return LBM_EINVAL;
     if (c->precision != LBM_PREC_FP32 &&
         (!std::isfinite(c->rho_ref) || !std::isfinite(c->g_ref)))
@@ -129,13 +129,15 @@ int make_inlet(const lbm_config *c, int32_t n_t, const double *ux, const double 
   {BX, BY, NY, NX, W, CP, 1, 0,                                                  \
    {(const void *)&step_kernel<CodecF32, BX, BY, NY, NX, W, CP>,                 \
     (const void *)&step_kernel<CodecF16, BX, BY, NY, NX, W, CP>,                 \
-    (const void *)&step_kernel<CodecBF16, BX, BY, NY, NX, W, CP>}}
+    (const void *)&step_kernel<CodecBF16, BX, BY, NY, NX, W, CP>,                \
+    (const void *)&step_kernel<CodecF16SR, BX, BY, NY, NX, W, CP>}}
 // two steps per launch: 64 x TY tiles, block 64 x NW
 #define LBM_PAIR(TY, NW, W, CP)                                                  \
   {64, NW, (TY) / (NW), 1, W, CP, 2, (NPOP - ((CP) & 8 ? 1 : 0)) * ((TY) + 2) * PAIR_W * 4, \
    {(const void *)&pair_kernel<CodecF32, TY, NW, W, CP>,                         \
     (const void *)&pair_kernel<CodecF16, TY, NW, W, CP>,                         \
-    (const void *)&pair_kernel<CodecBF16, TY, NW, W, CP>}}
+    (const void *)&pair_kernel<CodecBF16, TY, NW, W, CP>,                        \
+    (const void *)&pair_kernel<CodecF16SR, TY, NW, W, CP>}}
 
 static const TileShape kShapes[] = {
     LBM_SHAPE(64, 4, 1, 1, 1, 0),  LBM_SHAPE(128, 2, 1, 1, 1, 0), LBM_SHAPE(256, 1, 1, 1, 1, 0),
@@ -188,9 +190,10 @@ int launch_step(int shape, int prec, int grid, hipStream_t st, const JetDesc *je
 }
 
 static const void *aa_fn(int prec) {
-  static const void *fn[3] = {(const void *)&aa_kernel<CodecF32>,
+  static const void *fn[4] = {(const void *)&aa_kernel<CodecF32>,
                               (const void *)&aa_kernel<CodecF16>,
-                              (const void *)&aa_kernel<CodecBF16>};
+                              (const void *)&aa_kernel<CodecBF16>,
+                              (const void *)&aa_kernel<CodecF16SR>};
   return fn[codec_index(prec)];
 }
 
@@ -234,6 +237,7 @@ int launch_init(int prec, hipStream_t st, const JetDesc *d, const lbm_config *c,
                 const float4 *state, float4 u0) {
   if (prec == LBM_PREC_FP32) init_t<CodecF32>(st, d, c, step, view, state, u0);
   else if (prec == LBM_PREC_FP16DEV) init_t<CodecF16>(st, d, c, step, view, state, u0);
+  else if (prec == LBM_PREC_FP16SR) init_t<CodecF16SR>(st, d, c, step, view, state, u0);
   else init_t<CodecBF16>(st, d, c, step, view, state, u0);
   LBM_HIP(hipGetLastError());
   return LBM_OK;
@@ -248,6 +252,7 @@ int launch_ghost_fill(int prec, hipStream_t st, const JetDesc *d, const lbm_conf
                       int64_t step, int32_t view) {
   if (prec == LBM_PREC_FP32) ghost_t<CodecF32>(st, d, c, step, view);
   else if (prec == LBM_PREC_FP16DEV) ghost_t<CodecF16>(st, d, c, step, view);
+  else if (prec == LBM_PREC_FP16SR) ghost_t<CodecF16SR>(st, d, c, step, view);
   else ghost_t<CodecBF16>(st, d, c, step, view);
   LBM_HIP(hipGetLastError());
   return LBM_OK;
@@ -263,6 +268,7 @@ int launch_moments(int prec, hipStream_t st, const JetDesc *d, const lbm_config 
                    int64_t step, int32_t view, float4 *out) {
   if (prec == LBM_PREC_FP32) moments_t<CodecF32>(st, d, c, step, view, out);
   else if (prec == LBM_PREC_FP16DEV) moments_t<CodecF16>(st, d, c, step, view, out);
+  else if (prec == LBM_PREC_FP16SR) moments_t<CodecF16SR>(st, d, c, step, view, out);
   else moments_t<CodecBF16>(st, d, c, step, view, out);
   LBM_HIP(hipGetLastError());
   return LBM_OK;
@@ -278,6 +284,7 @@ int launch_profiles(int prec, hipStream_t st, const JetDesc *d, const lbm_config
                     int64_t step, int32_t view, float2 *out) {
   if (prec == LBM_PREC_FP32) profiles_t<CodecF32>(st, d, c, step, view, out);
   else if (prec == LBM_PREC_FP16DEV) profiles_t<CodecF16>(st, d, c, step, view, out);
+  else if (prec == LBM_PREC_FP16SR) profiles_t<CodecF16SR>(st, d, c, step, view, out);
   else profiles_t<CodecBF16>(st, d, c, step, view, out);
   LBM_HIP(hipGetLastError());
   return LBM_OK;
@@ -294,6 +301,7 @@ int launch_conservation(int prec, hipStream_t st, const JetDesc *d, int64_t node
   (void)nodes;
   if (prec == LBM_PREC_FP32) cons_t<CodecF32>(st, d, step, view, partial, nblocks);
   else if (prec == LBM_PREC_FP16DEV) cons_t<CodecF16>(st, d, step, view, partial, nblocks);
+  else if (prec == LBM_PREC_FP16SR) cons_t<CodecF16SR>(st, d, step, view, partial, nblocks);
   else cons_t<CodecBF16>(st, d, step, view, partial, nblocks);
   LBM_HIP(hipGetLastError());
   hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(RED_THREADS), 0, st, partial, nblocks,
@@ -312,6 +320,7 @@ int launch_decode(int prec, hipStream_t st, const JetDesc *d, const lbm_config *
                   float *out) {
   if (prec == LBM_PREC_FP32) decode_t<CodecF32>(st, d, c, step, view, out);
   else if (prec == LBM_PREC_FP16DEV) decode_t<CodecF16>(st, d, c, step, view, out);
+  else if (prec == LBM_PREC_FP16SR) decode_t<CodecF16SR>(st, d, c, step, view, out);
   else decode_t<CodecBF16>(st, d, c, step, view, out);
   LBM_HIP(hipGetLastError());
   return LBM_OK;
@@ -327,6 +336,7 @@ int launch_encode(int prec, hipStream_t st, const JetDesc *d, const lbm_config *
                   const float *in) {
   if (prec == LBM_PREC_FP32) encode_t<CodecF32>(st, d, c, step, view, in);
   else if (prec == LBM_PREC_FP16DEV) encode_t<CodecF16>(st, d, c, step, view, in);
+  else if (prec == LBM_PREC_FP16SR) encode_t<CodecF16SR>(st, d, c, step, view, in);
   else encode_t<CodecBF16>(st, d, c, step, view, in);
   LBM_HIP(hipGetLastError());
   return LBM_OK;

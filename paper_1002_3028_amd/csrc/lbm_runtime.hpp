@@ -56,7 +56,7 @@ int make_inlet(const lbm_config *c, int32_t n_t, const double *ux, const double 
 // (2: the LDS-blocked two-step kernel).
 struct TileShape {
   int bx, by, ny, nx, waves, cache, steps, lds;
-  const void *fn[3];  // FP32, FP16-dev, BF16-dev
+  const void *fn[4];  // FP32, FP16-dev, BF16-dev, FP16-dev rounded stochastically
 };
 const TileShape *tile_shapes(int *count);
 int default_tile_shape(int prec);

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "liblbm_hip.so")
 
 ABI_VERSION = 2
 OK, EINVAL, ENOMEM, EUNSTABLE, EDEVICE, ESTATE = 0, -1, -2, -3, -4, -5
-PRECISION = {"fp32": 1, "fp16": 2, "bf16": 3}
+PRECISION = {"fp32": 1, "fp16": 2, "bf16": 3, "fp16sr": 4}
 BC = {"inlet": 0, "outflow": 1, "periodic": 2, "axis": 3, "freeslip": 4, "wall": 5, "eq": 6}
 LAYOUT = {"two": 0, "single": 1}  # two buffers, or one updated in place
 

@@ -34,7 +34,8 @@ def _moments_after(batch, slots):
 
 @pytest.mark.parametrize("precision,cohort,streams", [
     ("fp32", 0, 2), ("fp16", 0, 2), ("fp32", 1 << 20, 1), ("fp32", 1 << 20, 2),
-    ("fp32", 1 << 20, 3), ("fp16", 3 << 20, 1), ("fp16", 3 << 20, 2), ("fp16", 1 << 20, 4)])
+    ("fp32", 1 << 20, 3), ("fp16", 3 << 20, 1), ("fp16", 3 << 20, 2), ("fp16", 1 << 20, 4),
+    ("fp16sr", 1 << 20, 2)])
 def test_alone_equals_in_mix(precision, cohort, streams):
     """cohort = 0 puts every jet in one launch; a small cohort limit splits
     them into several cache-sized cohorts, run one after another on one

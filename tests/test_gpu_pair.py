@@ -71,7 +71,7 @@ def test_pair_shapes_compiled():
         assert inf["lds"] == planes * (inf["by"] * inf["ny"] + 2) * 66 * 4
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp16", "bf16"])
+@pytest.mark.parametrize("precision", ["fp32", "fp16", "bf16", "fp16sr"])
 @pytest.mark.parametrize("case", CASES)
 def test_pair_equals_single(case, precision):
     for nx, nr in GRIDS:

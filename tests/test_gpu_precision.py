@@ -85,7 +85,8 @@ def test_small_jet_16bit_storage():
     p, inlet, steps = inputs.workload_small()
     ref = _run_ref(p, inlet, steps)
     errs = {}
-    for prec, g_ref in (("fp32", 0.0), ("fp16", 0.0), ("fp16", 0.5), ("bf16", 0.0)):
+    for prec, g_ref in (("fp32", 0.0), ("fp16", 0.0), ("fp16", 0.5), ("bf16", 0.0),
+                        ("fp16sr", 0.0)):
         errs[f"{prec}/g_ref={g_ref}"] = field_errors(_run_gpu(p, inlet, steps, prec, g_ref), ref)
     print(json.dumps(errs, indent=1))
     _record("128x32x500", errs)
@@ -96,6 +97,7 @@ def test_small_jet_16bit_storage():
     # where binary16 is densest: worse for a jet into cold ambient
     assert errs["fp16/g_ref=0.5"]["profile"] < 5e-3
     assert errs["bf16/g_ref=0.0"]["profile"] < 2e-2
+    assert errs["fp16sr/g_ref=0.0"]["profile"] < 1e-3
 
 
 def test_downscaled_twin_16bit_storage():
@@ -109,13 +111,16 @@ def test_downscaled_twin_16bit_storage():
     m32 = _run_gpu(p, inlet, steps, "fp32")
     m16 = _run_gpu(p, inlet, steps, "fp16")
     mbf = _run_gpu(p, inlet, steps, "bf16")
+    msr = _run_gpu(p, inlet, steps, "fp16sr")
     errs = {"fp32": field_errors(m32, ref), "fp16": field_errors(m16, ref),
-            "bf16": field_errors(mbf, ref), "fp16_vs_fp32": field_errors(m16, m32)}
+            "bf16": field_errors(mbf, ref), "fp16sr": field_errors(msr, ref),
+            "fp16_vs_fp32": field_errors(m16, m32)}
     print(json.dumps(errs, indent=1))
     _record("1024x256x1000", errs)
     assert errs["fp32"]["u"] < 1e-3 and errs["fp32"]["T"] < 1e-3
     assert errs["fp32"]["profile"] < 5e-4
     assert errs["fp16"]["profile"] < 1e-3
+    assert errs["fp16sr"]["profile"] < 1e-3
     assert errs["bf16"]["profile"] < 2e-2
 
 
@@ -127,7 +132,7 @@ def test_16bit_rest_state_exact():
     p = tiny_params(64, 16, "closed", 1)
     p["body_force_x"] = 0.0
     p["T0"] = 0.5
-    for prec in ("fp16", "bf16"):
+    for prec in ("fp16", "bf16", "fp16sr"):
         with lbm.Solver(p, prec, g_ref=0.5) as s:
             s.step(100)
             m = s.moments()

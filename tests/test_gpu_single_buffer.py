@@ -55,7 +55,7 @@ def _inlet(p, seed):
     return noisy_inlet(p["nr"], 5, seed) if p["bc"][0] == "inlet" else None
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp16", "bf16"])
+@pytest.mark.parametrize("precision", ["fp32", "fp16", "bf16", "fp16sr"])
 @pytest.mark.parametrize("case", CASES)
 def test_single_equals_two_buffers(case, precision):
     for nx, nr in GRIDS:
