@@ -65,7 +65,7 @@ enum lbm_precision {
   LBM_PREC_FP16SR = 4    /* binary16 of the same deviations, rounded
                             stochastically: up with the probability of the
                             discarded fraction, the random number a hash of
-                            the value and the plane (reproducible)          */
+                            the value's bits (reproducible)                 */
 };
 
 /* Edge rules, per side: 0 = x0 (i = -1), 1 = x1 (i = nx), 2 = r0 (j = -1),

@@ -138,11 +138,11 @@ struct CodecF16 {
   }
 };
 // binary16 deviations with stochastic rounding: the magnitude rounds toward
-// zero after adding u ulp, u in [0, 1) a hash of the value's bits and of the
-// plane's offset, so it rounds up with (about) the probability of the
-// discarded fraction and the rounding errors of values that keep returning do
-// not add up.  The hash makes it reproducible: the same value rounds the same
-// way wherever it is encoded.  Decoding is binary16's.
+// zero after adding u times its binary16 spacing, u in [0, 1) a hash of the
+// value's bits, so it rounds up with (about) the probability of the discarded
+// fraction and the rounding errors of values that keep returning do not add
+// up.  The hash makes it reproducible: the same value rounds the same way
+// wherever it is encoded.  Decoding is binary16's.
 struct CodecF16SR {
   using T = _Float16;
   static constexpr bool dev = true;
@@ -151,20 +151,18 @@ struct CodecF16SR {
   }
   __device__ static __forceinline__ T enc(float v, float off, float one) {
     const float x = __builtin_fmaf(v, one, -off);
-    const float a = fabsf(x);
-    // the lowbias32 integer hash (C. Wellons, hash-prospector) of the bits
-    uint32_t h = __builtin_bit_cast(uint32_t, x) ^ (__builtin_bit_cast(uint32_t, off) * 0x9E3779B9u);
-    h ^= h >> 16;
-    h *= 0x7feb352du;
+    const uint32_t xb = __builtin_bit_cast(uint32_t, x);
+    // two multiply-xorshift rounds (the constants of the lowbias32 mixer of
+    // C. Wellons' hash-prospector); the top 24 bits give u
+    uint32_t h = xb * 0x7feb352du;
     h ^= h >> 15;
     h *= 0x846ca68bu;
-    h ^= h >> 16;
-    const float u = (float)(h >> 8) * (1.0f / 16777216.0f);
-    // binary16 spacing at a: 2^(e - 10), e its binade (at least -14: subnormals)
-    int e = (int)((__builtin_bit_cast(uint32_t, a) >> 23) & 0xff) - 127;
-    e = e < -14 ? -14 : e;
-    const float ulp = __builtin_bit_cast(float, (uint32_t)(e - 10 + 127) << 23);
-    const T m = __builtin_amdgcn_cvt_pkrtz(__builtin_fmaf(u, ulp, a), 0.0f)[0];
+    const float u = (float)(h >> 8);  // u * 2^24
+    // binary16 spacing of |x|: its binade times 2^-10, at least 2^-24
+    const uint32_t ab = xb & 0x7fffffffu;
+    const float ulp = fmaxf(__builtin_bit_cast(float, ab & 0x7f800000u) * 0x1p-34f, 0x1p-48f);
+    const T m = __builtin_amdgcn_cvt_pkrtz(
+        __builtin_fmaf(u, ulp, __builtin_bit_cast(float, ab)), 0.0f)[0];
     return x < 0.0f ? -m : m;
   }
 };
