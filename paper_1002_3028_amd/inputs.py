@@ -182,10 +182,13 @@ def arrival_trace(n: int = 2000, seed: int = 3, rate: float = 10.0, hoop: int = 
 
 
 def perturbed_state(nx: int, nr: int, seed: int, r0: float = 0.0, amp: float = 0.02,
-                    T_mean: float = 0.5, T_amp: float = 0.2):
+                    T_mean: float = 0.5, T_amp: float = 0.2, noise: float = 0.0):
     """Smooth random non-uniform state (rho, ux, ur, T), each (nr, nx): a few
     random Fourier modes in x times smooth radial bumps; ur vanishes towards
-    the axis.  Used for the closed-domain and parity checks."""
+    the axis.  Used for the closed-domain and parity checks.  noise > 0 adds
+    independent Gaussian values of noise times each field's amplitude at
+    every node (drawn after the modes, so the smooth part does not change),
+    which makes every node differ from its neighbours."""
     rng = np.random.default_rng(seed)
     x = (np.arange(nx) + 0.5) / nx
     r = (np.arange(nr) + 0.5) / nr
@@ -205,4 +208,7 @@ def perturbed_state(nx: int, nr: int, seed: int, r0: float = 0.0, amp: float = 0
     ux = field(amp)
     ur = field(amp) * R
     T = T_mean + field(T_amp)
+    if noise > 0.0:  # (ur's noise also scaled by R)
+        for a, scale in ((rho, amp), (ux, amp), (ur, amp * R), (T, T_amp)):
+            a += (noise * scale) * rng.standard_normal(a.shape)
     return rho, ux, ur, T
