@@ -64,8 +64,9 @@ enum lbm_precision {
   LBM_PREC_BF16DEV = 3,  /* bfloat16 of the same deviations                  */
   LBM_PREC_FP16SR = 4    /* binary16 of the same deviations, rounded
                             stochastically: up with the probability of the
-                            discarded fraction, the random number a hash of
-                            the value's bits (reproducible)                 */
+                            discarded fraction (values binary16 holds are
+                            kept), the random number a hash of the value's
+                            bits (reproducible)                             */
 };
 
 /* Edge rules, per side: 0 = x0 (i = -1), 1 = x1 (i = nx), 2 = r0 (j = -1),

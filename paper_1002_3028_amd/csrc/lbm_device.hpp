@@ -138,11 +138,14 @@ struct CodecF16 {
   }
 };
 // binary16 deviations with stochastic rounding: the magnitude rounds toward
-// zero after adding u times its binary16 spacing, u in [0, 1) a hash of the
-// value's bits, so it rounds up with (about) the probability of the discarded
-// fraction and the rounding errors of values that keep returning do not add
-// up.  The hash makes it reproducible: the same value rounds the same way
-// wherever it is encoded.  Decoding is binary16's.
+// zero after adding r times its FP32 ulp, r in [0, 2^13) a hash of the value's
+// bits.  Where binary16 is normal its spacing is 2^13 FP32 ulps, the sum is
+// exact, and the value rounds up with exactly the probability of the discarded
+// fraction (values binary16 holds stay as they are); below 2^-14 the offset
+// spans the fixed spacing 2^-24 in steps of 2^-37.  The rounding errors of
+// values that keep returning therefore do not add up.  The hash makes it
+// reproducible: the same value rounds the same way wherever it is encoded.
+// Decoding is binary16's.
 struct CodecF16SR {
   using T = _Float16;
   static constexpr bool dev = true;
@@ -152,17 +155,19 @@ struct CodecF16SR {
   __device__ static __forceinline__ T enc(float v, float off, float one) {
     const float x = __builtin_fmaf(v, one, -off);
     const uint32_t xb = __builtin_bit_cast(uint32_t, x);
-    // two multiply-xorshift rounds (the constants of the lowbias32 mixer of
-    // C. Wellons' hash-prospector); the top 24 bits give u
-    uint32_t h = xb * 0x7feb352du;
+    // the lowbias32 mixer of C. Wellons' hash-prospector (its last xorshift
+    // does not reach the top 13 bits, which give r); the first xorshift
+    // carries the high bits of the value into every bit of r
+    uint32_t h = xb ^ (xb >> 16);
+    h *= 0x7feb352du;
     h ^= h >> 15;
     h *= 0x846ca68bu;
-    const float u = (float)(h >> 8);  // u * 2^24
-    // binary16 spacing of |x|: its binade times 2^-10, at least 2^-24
+    const float r = (float)(h >> 19);
+    // FP32 ulp of |x| (its binade times 2^-23), at least 2^-37
     const uint32_t ab = xb & 0x7fffffffu;
-    const float ulp = fmaxf(__builtin_bit_cast(float, ab & 0x7f800000u) * 0x1p-34f, 0x1p-48f);
+    const float ulp = fmaxf(__builtin_bit_cast(float, ab & 0x7f800000u) * 0x1p-23f, 0x1p-37f);
     const T m = __builtin_amdgcn_cvt_pkrtz(
-        __builtin_fmaf(u, ulp, __builtin_bit_cast(float, ab)), 0.0f)[0];
+        __builtin_fmaf(r, ulp, __builtin_bit_cast(float, ab)), 0.0f)[0];
     return x < 0.0f ? -m : m;
   }
 };

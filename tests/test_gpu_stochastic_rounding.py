@@ -1,0 +1,108 @@
+"""FP16 storage with stochastic rounding (fp16sr), through the C-ABI: values
+written with lbm_set_populations are encoded by the device codec and read
+back with lbm_get_populations.  The temperature planes with g_ref = 0 store
+the value itself (zero offset), so the stored binary16 number is seen
+directly.  Properties checked:
+
+* every stored value is one of the two binary16 neighbours of the value
+  (rounded toward zero, or one spacing away from zero);
+* values that binary16 holds are stored unchanged (2^16 of them, normal and
+  subnormal, both signs);
+* the number of values rounded up matches the sum of their discarded
+  fractions within 5 standard deviations of that binomial sum (unbiased);
+* the same value rounds the same way wherever it is stored, and writing the
+  same data again gives the same bits (reproducible).
+"""
+import numpy as np
+import pytest
+
+from gpu_common import require_gpu, tiny_params
+
+pytestmark = pytest.mark.gpu
+
+NX, NR = 128, 128
+N = 4 * NX * NR  # values per round trip (four g planes)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    require_gpu()
+
+
+@pytest.fixture(scope="module")
+def solver():
+    from paper_1002_3028_amd import lbm
+    p = tiny_params(NX, NR, "jet", hoop=1)
+    with lbm.Solver(p, "fp16sr", rho_ref=1.0, g_ref=0.0) as s:
+        yield s
+
+
+def _round_trip(s, g_values):
+    w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
+    f = np.broadcast_to(w[:, None, None], (9, NR, NX)).copy()
+    s.set_populations(f, np.asarray(g_values, np.float64).reshape(4, NR, NX), 0)
+    return s.get_populations()[1].reshape(-1)
+
+
+def _neighbours(v):
+    """binary16 value of v rounded toward zero, and the next one away from zero."""
+    h = v.astype(np.float16)
+    lo = np.where(np.abs(h.astype(np.float64)) > np.abs(v), np.nextafter(h, np.float16(0)), h)
+    hi = np.nextafter(lo, np.where(v < 0, np.float16(-np.inf), np.float16(np.inf)).astype(np.float16))
+    return lo.astype(np.float64), hi.astype(np.float64)
+
+
+def test_representable_values_unchanged(solver):
+    rng = np.random.default_rng(11)
+    m = rng.integers(1024, 2048, N)
+    e = rng.integers(-14, 0, N)
+    v = m * 2.0 ** (e - 10)
+    sub = rng.random(N) < 0.25  # a quarter subnormal: n * 2^-24
+    v[sub] = rng.integers(0, 1024, int(sub.sum())) * 2.0 ** -24
+    v *= np.where(rng.integers(0, 2, N) == 1, -1.0, 1.0)
+    got = _round_trip(solver, v)
+    assert np.array_equal(got, v), int(np.sum(got != v))
+
+
+def test_neighbours_and_unbiased(solver):
+    rng = np.random.default_rng(12)
+    # magnitudes log-uniform over [2^-20, 2^-2] (normal and subnormal binary16),
+    # first rounded to FP32 so that the device sees the same value
+    v = (2.0 ** rng.uniform(-20, -2, N) * np.where(rng.integers(0, 2, N) == 1, -1.0, 1.0))
+    v = v.astype(np.float32).astype(np.float64)
+    got = _round_trip(solver, v)
+    lo, hi = _neighbours(v)
+    assert np.all((got == lo) | (got == hi))
+    up = got == hi
+    phi = (np.abs(v) - np.abs(lo)) / (np.abs(hi) - np.abs(lo))
+    normal = np.abs(lo) >= 2.0 ** -14
+    for sel in (normal, ~normal):
+        dev = float(np.sum(up[sel]) - np.sum(phi[sel]))
+        sd = float(np.sqrt(np.sum(phi[sel] * (1 - phi[sel]))))
+        print(f"{int(sel.sum())} values: {int(up[sel].sum())} up, expected {phi[sel].sum():.1f} "
+              f"+- {sd:.1f}")
+        # (below 2^-14 the offset steps are 2^-13 of the spacing: allow that)
+        assert abs(dev) < 5 * sd + 2.0 ** -13 * sel.sum()
+
+
+@pytest.mark.parametrize("phi", [j / 16 for j in range(1, 16)])
+def test_fixed_fraction(solver, phi):
+    """Values that all sit the same fraction phi of a spacing above a binary16
+    number (every mantissa of 14 binades, both signs: 28 672 distinct values)
+    round up in a fraction phi of cases."""
+    m, e, sg = np.meshgrid(np.arange(1024, 2048), np.arange(-14, 0), [1.0, -1.0], indexing="ij")
+    v = (sg * (m + phi) * 2.0 ** (e - 10)).reshape(-1)
+    n = v.size
+    up = (np.abs(_round_trip(solver, np.resize(v, N))) > np.abs(np.resize(v, N)))[:n]
+    sd = np.sqrt(phi * (1 - phi) / n)
+    print(f"phi {phi}: {up.mean():.4f} up of {n} (sd {sd:.4f})")
+    assert abs(up.mean() - phi) < 5 * sd
+
+
+def test_reproducible(solver):
+    rng = np.random.default_rng(13)
+    base = (rng.uniform(-0.3, 0.3, N // 8)).astype(np.float32).astype(np.float64)
+    v = np.tile(base, 8)  # each value at eight places, in every plane
+    a = _round_trip(solver, v)
+    assert np.array_equal(a.reshape(8, -1), np.broadcast_to(a[: N // 8], (8, N // 8)))
+    assert np.array_equal(_round_trip(solver, v), a)
