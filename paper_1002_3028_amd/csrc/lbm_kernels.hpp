@@ -50,6 +50,24 @@ __device__ __forceinline__ T elem(const typename Pack<T, NX>::vec &v, int e) {
   else return v[e];
 }
 
+// Tile walk of every step kernel.  The dispatcher deals workgroups round-robin
+// over the eight XCDs, so workgroup b runs on XCD b mod 8.  Each XCD takes an
+// equal contiguous share of the tile list, [ntiles x / 8, ntiles (x + 1) / 8),
+// and its gridDim.x / 8 workgroups walk it with that stride.  The tiles whose
+// x-shifted pulls share columns then sit in one L2, and no XCD idles while
+// the others still hold tiles, whatever ntiles is against the grid size.
+// With one workgroup per tile (rounded up to a multiple of 8) a workgroup gets
+// at most one tile.  The grid is a multiple of 8.
+struct TileWalk {
+  int32_t first, end, stride;
+};
+__device__ __forceinline__ TileWalk tile_walk(int32_t ntiles) {
+  const int32_t b = (int32_t)blockIdx.x, x = b & 7;
+  const int32_t lo = (int32_t)(((int64_t)ntiles * x) >> 3);
+  const int32_t hi = (int32_t)(((int64_t)ntiles * (x + 1)) >> 3);
+  return {lo + (b >> 3), hi, (int32_t)(gridDim.x >> 3)};
+}
+
 // ---------------------------------------------------------------------------
 // The fused collide-and-stream step over a flat tile list covering every
 // active jet.  A tile is (BX * NX) x (BY * NY) nodes: thread (tx, ty) handles
@@ -58,11 +76,8 @@ __device__ __forceinline__ T elem(const typename Pack<T, NX>::vec &v, int e) {
 // current, so every thread reads each plane with one buffer load of NX
 // elements and writes with one buffer store; edge nodes then write the
 // ghost values of the next step that they are the source of.
-// Workgroups walk the tile list with a grid stride; within each round the
-// tiles handed to one XCD (workgroup id mod 8) are contiguous, so the
-// columns that x-shifted pulls share with the neighbouring tile stay in one
-// L2.  W is the occupancy target (waves per SIMD) for register allocation;
-// CP selects non-temporal stores (bit 0) and loads (bit 1).
+// Workgroups walk the tile list as tile_walk() assigns it.  W is the
+// occupancy target (waves per SIMD) for register allocation; CP selects non-temporal stores (bit 0) and loads (bit 1).
 // The jet's state after s steps lives in buf[(s + flip) & 1], where flip is
 // the descriptor's value toggled by `tog` (the parity of the two-step
 // launches issued since the descriptor was last advanced); the step taken
@@ -80,10 +95,8 @@ __global__ __launch_bounds__(BX *BY) __attribute__((amdgpu_waves_per_eu(W, 8))) 
   using VT = typename Pack<T, NX>::vec;
   const int32_t njets = hdr->njets;
   const int32_t ntiles = tile_start[njets];
-  const int32_t G = gridDim.x;  // a multiple of 8
-  const int32_t per_xcd = G >> 3;
-  const int32_t b = blockIdx.x;
-  for (int32_t t = (b & 7) * per_xcd + (b >> 3); t < ntiles; t += G) {
+  const TileWalk tw = tile_walk(ntiles);
+  for (int32_t t = tw.first; t < tw.end; t += tw.stride) {
     int32_t jid = 0;
     if (njets > 1) {  // last jet whose first tile is <= t
       int32_t lo = 0, hi = njets - 1;
@@ -309,10 +322,8 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(W, 8)))
   const int lane = (int)threadIdx.x, wave = (int)threadIdx.y;
   const int32_t njets = hdr->njets;
   const int32_t ntiles = tile_start[njets];
-  const int32_t G = gridDim.x;  // a multiple of 8
-  const int32_t per_xcd = G >> 3;
-  const int32_t b = blockIdx.x;
-  for (int32_t t = (b & 7) * per_xcd + (b >> 3); t < ntiles; t += G) {
+  const TileWalk tw = tile_walk(ntiles);
+  for (int32_t t = tw.first; t < tw.end; t += tw.stride) {
     int32_t jid = 0;
     if (njets > 1) {  // last jet whose first tile is <= t
       int32_t lo = 0, hi = njets - 1;
@@ -504,10 +515,8 @@ __global__ __launch_bounds__(256) void aa_kernel(
   const int lane = (int)threadIdx.x, wave = (int)threadIdx.y;
   const int32_t njets = hdr->njets;
   const int32_t ntiles = tile_start[njets];
-  const int32_t G = gridDim.x;  // a multiple of 8
-  const int32_t per_xcd = G >> 3;
-  const int32_t b = blockIdx.x;
-  for (int32_t t = (b & 7) * per_xcd + (b >> 3); t < ntiles; t += G) {
+  const TileWalk tw = tile_walk(ntiles);
+  for (int32_t t = tw.first; t < tw.end; t += tw.stride) {
     int32_t jid = 0;
     if (njets > 1) {  // last jet whose first tile is <= t
       int32_t lo = 0, hi = njets - 1;
