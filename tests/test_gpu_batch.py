@@ -184,3 +184,29 @@ def test_unstable_jet_fails_alone():
         assert e.value.code == lbm.EUNSTABLE
     for key in ref:
         assert np.array_equal(m[key], ref[key])
+
+
+@pytest.mark.parametrize("layout,steps_per_launch", [("two", 1), ("two", 2), ("single", 1)])
+def test_any_grid_size(layout, steps_per_launch):
+    """The tile walk hands every tile to exactly one workgroup whatever the grid
+    size is against the tile count: grids from 8 workgroups (one per XCD, each
+    walking its XCD's whole share) to 4096 (most of them idle) give the bits of
+    the default grid, for the one-step, two-step and single-buffer kernels."""
+    from paper_1002_3028_amd import lbm
+    infos = lbm.tile_shape_infos()
+    shape = [q for q, i in enumerate(infos) if i["steps"] == steps_per_launch][0]
+    jets = _jets()
+    runs = []
+    for grid in (0, 8, 24, 136, 1288, 4096):
+        with lbm.Batch(1 << 28, 8, "fp32", layout=layout) as b:
+            b.set_launch(shape, grid)
+            slots = [b.admit(p, inlet, steps) for p, inlet, steps in jets]
+            for _ in range(4):
+                b.run(30)
+            assert [b.poll(s) for s in slots] == [steps for _, _, steps in jets], grid
+            runs.append((grid, [b.moments(s) for s in slots]))
+    base = runs[0][1]
+    for grid, ms in runs[1:]:
+        for q, (m, m0) in enumerate(zip(ms, base)):
+            for key in m0:
+                assert np.array_equal(m[key], m0[key]), (grid, q, key)
