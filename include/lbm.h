@@ -177,8 +177,8 @@ int lbm_probe_copy(void *dst, const void *src, size_t bytes, void *hip_stream);
  * A batch owns up to max_slots resident jets whose population buffers are
  * carved out of budget_bytes of device memory.  lbm_batch_run advances every
  * active jet by up to k steps: the active jets are grouped into cohorts of
- * at most cohort_bytes of buffers (default 112 MiB, so that the two cohorts
- * in flight at once stay in the Infinity Cache), and each cohort gets k
+ * at most cohort_bytes of buffers (default 128 MiB, so that the two cohorts
+ * in flight at once fill the 256 MiB Infinity Cache), and each cohort gets k
  * steps of one persistent launch per step over all its jets (HIP graphs),
  * cohorts alternating between two streams (lbm_batch_set_streams).  A jet
  * stops at its own target step count.  Each jet's result is bitwise the
@@ -216,7 +216,7 @@ int lbm_batch_active(const lbm_batch *b, int32_t *n_active, size_t *bytes_used);
  * holds at once for that kernel). */
 int lbm_batch_set_launch(lbm_batch *b, int32_t tile_shape, int32_t workgroups);
 /* Cohort size limit in bytes of population buffers (0: all jets together;
- * default 112 MiB, so that the two cohorts running at once fit the 256 MB
+ * default 128 MiB, so that the two cohorts running at once fill the 256 MiB
  * Infinity Cache). */
 int lbm_batch_set_cohort_bytes(lbm_batch *b, size_t bytes);
 /* Streams the cohorts of a run are spread over, 1 to 4: cohort c runs on

@@ -85,8 +85,8 @@ struct lbm_batch {
   int32_t max_cohorts = 0;
   int32_t n_cohorts = 0;
   // 0: one cohort.  Two cohorts run at once (two streams), and together they
-  // stay inside the 256 MB Infinity Cache.
-  size_t cohort_bytes = size_t(112) << 20;
+  // fill the 256 MiB Infinity Cache.
+  size_t cohort_bytes = size_t(128) << 20;
   int32_t *d_flags = nullptr;
   Scratch scratch;
   std::vector<int32_t> active;  // slots in the compact list, in order

@@ -65,7 +65,7 @@ def batch64(args):
             b.admit(p, inlet, args.steps + 100)
         # the runtime's grouping: slot order, a new cohort whenever the next
         # jet would take the current one past the limit
-        limit, cohorts, cur = 112 << 20, 1, 0
+        limit, cohorts, cur = 128 << 20, 1, 0
         for p, _, _ in jets:
             jb = b.jet_bytes(p)
             if cur and cur + jb > limit:
