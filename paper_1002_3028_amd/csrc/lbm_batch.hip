@@ -9,6 +9,7 @@
 // jets, so the captured graph of k steps of a cohort is replayed as jets come
 // and go.
 #include <algorithm>
+#include <cstring>
 #include <map>
 #include <tuple>
 
@@ -88,6 +89,11 @@ struct lbm_batch {
   // fill the 256 MiB Infinity Cache.
   size_t cohort_bytes = size_t(128) << 20;
   int32_t *d_flags = nullptr;
+  // pinned staging of what rebuild uploads (cohort after cohort, compact), so
+  // that the uploads are asynchronous copies ordered before the launches
+  JetDesc *h_jets = nullptr;   // max_slots descriptors
+  int32_t *h_tiles = nullptr;  // max_slots + max_cohorts tile prefix sums
+  BatchHdr *h_hdr = nullptr;   // max_cohorts
   Scratch scratch;
   std::vector<int32_t> active;  // slots in the compact list, in order
   bool dirty = true;
@@ -146,26 +152,31 @@ int rebuild(lbm_batch *b) {
     bytes.back() += sl.bytes;
     b->active.push_back(s);
   }
+  // the launches queued so far read the device lists and the last rebuild's
+  // copies read the staging: wait for both before anything is rewritten
   LBM_HIP(hipStreamSynchronize(b->stream));
   const int32_t prev = b->n_cohorts;
   b->n_cohorts = jets.back().empty() && jets.size() == 1 ? 0 : (int32_t)jets.size();
-  std::vector<BatchHdr> hdr((size_t)b->max_cohorts, BatchHdr{0, {0, 0, 0}});
-  for (int32_t c = 0; c < b->n_cohorts; ++c) {
-    const int32_t n = (int32_t)jets[c].size();
-    hdr[c].njets = n;
-    LBM_HIP(hipMemcpy(b->d_jets + (size_t)c * ms, jets[c].data(), n * sizeof(JetDesc),
-                      hipMemcpyHostToDevice));
-    LBM_HIP(hipMemcpy(b->d_tiles + (size_t)c * (ms + 1), start[c].data(),
-                      start[c].size() * sizeof(int32_t), hipMemcpyHostToDevice));
-  }
-  // cohorts that emptied keep an empty tile list
-  const int32_t zero = 0;
-  for (int32_t c = b->n_cohorts; c < prev; ++c)
-    LBM_HIP(hipMemcpy(b->d_tiles + (size_t)c * (ms + 1), &zero, sizeof zero,
-                      hipMemcpyHostToDevice));
   const int32_t nh = std::max(prev, b->n_cohorts);
+  size_t jo = 0, to = 0;  // staging offsets
+  for (int32_t c = 0; c < nh; ++c) {
+    // cohorts that emptied keep an empty tile list
+    const int32_t n = c < b->n_cohorts ? (int32_t)jets[c].size() : 0;
+    b->h_hdr[c] = BatchHdr{n, {0, 0, 0}};
+    if (n > 0) std::memcpy(b->h_jets + jo, jets[c].data(), n * sizeof(JetDesc));
+    if (n > 0) std::memcpy(b->h_tiles + to, start[c].data(), (n + 1) * sizeof(int32_t));
+    else b->h_tiles[to] = 0;
+    if (n > 0)
+      LBM_HIP(hipMemcpyAsync(b->d_jets + (size_t)c * ms, b->h_jets + jo, n * sizeof(JetDesc),
+                             hipMemcpyHostToDevice, b->stream));
+    LBM_HIP(hipMemcpyAsync(b->d_tiles + (size_t)c * (ms + 1), b->h_tiles + to,
+                           (n + 1) * sizeof(int32_t), hipMemcpyHostToDevice, b->stream));
+    jo += n;
+    to += n + 1;
+  }
   if (nh > 0)
-    LBM_HIP(hipMemcpy(b->d_hdr, hdr.data(), nh * sizeof(BatchHdr), hipMemcpyHostToDevice));
+    LBM_HIP(hipMemcpyAsync(b->d_hdr, b->h_hdr, nh * sizeof(BatchHdr), hipMemcpyHostToDevice,
+                           b->stream));
   // persistent grid of fixed size (graphs stay valid as jets come and go):
   // by default the workgroups the device holds at once
   int32_t g = b->wg > 0 ? b->wg
@@ -244,7 +255,12 @@ int lbm_batch_create(size_t budget_bytes, int32_t max_slots, int32_t precision,
             hipMalloc(&b->d_slot_desc, max_slots * sizeof(JetDesc)) == hipSuccess &&
             hipMalloc(&b->d_tiles, mc * (max_slots + 1) * sizeof(int32_t)) == hipSuccess &&
             hipMalloc(&b->d_hdr, mc * sizeof(BatchHdr)) == hipSuccess &&
-            hipMalloc(&b->d_flags, max_slots * sizeof(int32_t)) == hipSuccess;
+            hipMalloc(&b->d_flags, max_slots * sizeof(int32_t)) == hipSuccess &&
+            hipHostMalloc(&b->h_jets, max_slots * sizeof(JetDesc), hipHostMallocDefault) ==
+                hipSuccess &&
+            hipHostMalloc(&b->h_tiles, (max_slots + mc) * sizeof(int32_t), hipHostMallocDefault) ==
+                hipSuccess &&
+            hipHostMalloc(&b->h_hdr, mc * sizeof(BatchHdr), hipHostMallocDefault) == hipSuccess;
   if (ok && hip_stream) {
     b->stream = (hipStream_t)hip_stream;
   } else if (ok) {
@@ -560,6 +576,9 @@ void lbm_batch_destroy(lbm_batch *b) {
   if (b->d_tiles) (void)hipFree(b->d_tiles);
   if (b->d_hdr) (void)hipFree(b->d_hdr);
   if (b->d_flags) (void)hipFree(b->d_flags);
+  if (b->h_jets) (void)hipHostFree(b->h_jets);
+  if (b->h_tiles) (void)hipHostFree(b->h_tiles);
+  if (b->h_hdr) (void)hipHostFree(b->h_hdr);
   if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
   if (b->fork) (void)hipEventDestroy(b->fork);
   for (int q = 0; q + 1 < lbm_batch::MAX_STREAMS; ++q) {
