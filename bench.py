@@ -167,10 +167,10 @@ def bench_serving(n_requests=200, precision="fp16"):
     from paper_1002_3028_amd import inputs, serve
 
     cap, _ = serve.serve(inputs.arrival_trace(n_requests, 3, rate=1.0), precision,
-                         16 << 30, 256, 50, realtime=False)
+                         16 << 30, 256, 100, realtime=False)
     rate = 0.7 * cap["requests_per_s"]
     run, _ = serve.serve(inputs.arrival_trace(n_requests, 3, rate=rate), precision,
-                         16 << 30, 256, 50, realtime=True)
+                         16 << 30, 256, 100, realtime=True)
     return {"requests": n_requests, "precision": precision,
             "capacity_req_per_s": cap["requests_per_s"], "capacity_glups": cap["glups"],
             "rate_req_per_s": round(rate, 3), "p50_s": run["p50_s"], "p99_s": run["p99_s"],

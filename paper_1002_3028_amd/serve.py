@@ -33,7 +33,7 @@ def percentile(xs, q):
 
 
 def serve(requests, precision: str = "fp16", budget_bytes: int = 16 << 30,
-          max_slots: int = 256, k_steps: int = 50, realtime: bool = True,
+          max_slots: int = 256, k_steps: int = 100, realtime: bool = True,
           tile_shape: int = -1, workgroups: int = 0, keep_profiles: bool = False,
           layout: str = "two", streams: int = 0, cohort_bytes: int = -1):
     """Run the request list [(arrival_s, params, inlet, steps), ...].
@@ -122,7 +122,7 @@ def main():
     ap.add_argument("--precision", default="fp16")
     ap.add_argument("--budget-gb", type=float, default=16.0)
     ap.add_argument("--slots", type=int, default=256)
-    ap.add_argument("--k", type=int, default=50)
+    ap.add_argument("--k", type=int, default=100)
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--layout", choices=["two", "single"], default="two")
     ap.add_argument("--streams", type=int, default=0, help="1 to 4 (0: the batch's default)")
