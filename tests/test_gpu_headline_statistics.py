@@ -4,9 +4,8 @@ i = nx/2 and nx-1; profile error ||d||_2 / ||ref||_2 per quantity), for the
 2048 x 512 jet (the benchmark's workload) and the 1024 x 256 twin of the
 4096 x 1024 jet, against the FP64 oracle.
 
-A chaotic LES jet makes such averages noisy: the same FP32 run started from a
-state perturbed by 1e-6 differs from itself by the realization floor (about
-1.8 % in u_x and 0.3 % in T on the twin).  A storage form passes if each
+A chaotic LES jet makes such averages noisy: the same FP32 run with its inlet
+rows perturbed by 1e-6 (relative) differs from itself by the realization floor.  A storage form passes if each
 error is within max(1 %, 1.5 x floor).  FP16 storage rounds the temperature
 populations with a bias that moves T far past the floor (an expected
 failure that reports its numbers); stochastic rounding (fp16sr) removes it.
@@ -57,13 +56,17 @@ def _err(a, b):
 
 
 def _gpu_run(p, inlet, precision, perturb=0.0):
+    """perturb > 0 scales the inlet rows of u_x and T by 1 + perturb N(0, 1).
+    The perturbation enters at every step, so rounding cannot erase it before
+    the jet forms, as it can erase one of the initial rest state."""
     from paper_1002_3028_amd import lbm
+    if perturb:
+        rng = np.random.default_rng(7)
+        ux, ur, T = (np.asarray(a, dtype=np.float64) for a in inlet)
+        inlet = (ux * (1.0 + perturb * rng.standard_normal(ux.shape)), ur,
+                 T * (1.0 + perturb * rng.standard_normal(T.shape)))
     with lbm.Solver(p, precision, graph_steps=EVERY) as s:
         s.set_inlet(*inlet)
-        if perturb:
-            n = p["nx"] * p["nr"]
-            rho = 1.0 + perturb * np.random.default_rng(7).standard_normal(n)
-            s.set_state(rho, np.zeros(n), np.zeros(n), np.zeros(n))
         return _averaged(s, precision + (" perturbed" if perturb else ""))
 
 
