@@ -5,8 +5,9 @@ i = nx/2 and nx-1; profile error ||d||_2 / ||ref||_2 per quantity), for the
 4096 x 1024 jet, against the FP64 oracle.
 
 A chaotic LES jet makes such averages noisy: the same FP32 run with its inlet
-rows perturbed by 1e-6 (relative) differs from itself by the realization floor.  A storage form passes if each
-error is within max(1 %, 1.5 x floor).  FP16 storage rounds the temperature
+rows perturbed by 1e-6 (relative) differs from itself by the realization
+floor.  A storage form passes if each error is within max(1 %, 1.5 x floor).
+FP16 storage rounds the temperature
 populations with a bias that moves T far past the floor (an expected
 failure that reports its numbers); stochastic rounding (fp16sr) removes it.
 
