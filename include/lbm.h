@@ -57,7 +57,9 @@ enum lbm_status {
   LBM_ESTATE = -5      /* call not valid in the handle's current state     */
 };
 
-/* Population storage.  Arithmetic is FP32 in every case. */
+/* Population storage.  Arithmetic is FP32 in every case.  (The value 0,
+ * FP64 populations, belongs to the FP64 CPU checker that exports the same
+ * calls; this library rejects it.) */
 enum lbm_precision {
   LBM_PREC_FP32 = 1,     /* 13 x 4 B per node                                */
   LBM_PREC_FP16DEV = 2,  /* binary16 of f_k - w_k rho_ref, g_k - g_ref/4     */
@@ -94,6 +96,35 @@ enum lbm_layout {
 
 typedef struct lbm_handle lbm_handle;
 
+/* Configuration of one jet.  Where each field comes from in the paper:
+ *   nx, nr        section 2.4: the half plane (x, r) discretised on a uniform
+ *                 lattice (the paper's run: 200 x 96 nodes);
+ *   r0            section 2.1: the axisymmetric form of eq. (1) in (x, r);
+ *                 node centres at r = r0 + j + 1/2 (a reading: the axis is
+ *                 a half-way mirror, so 1/r stays finite);
+ *   tau_nu,       text after eq. (1): nu = (tau_nu - 1/2)/3 and
+ *   tau_alpha     alpha = (tau_alpha - 1/2)/2 in lattice units;
+ *   cs, delta     section 2.2, eqs. (3)-(4): Smagorinsky constant C_s and
+ *                 filter width Delta;
+ *   pr_t          section 2.2, eq. (5): turbulent Prandtl number (0.3 to 1;
+ *                 0.3 in the validation runs of section 4.1);
+ *   table_n ..    section 2.3, eq. (6): nu(T), alpha(T) as multipliers of
+ *   t_hi          the base values on a uniform T grid (the paper's N2-Ar
+ *                 curves are not given; any table may be supplied);
+ *   bc            section 2.4 (inlet, symmetry axis, outflow, outer edge)
+ *                 and section 4.2 (a substrate wall at the far end);
+ *   wall_T        section 4.2: temperature of a wall (the substrate);
+ *                 NaN for an adiabatic wall;
+ *   eq_state      not in the paper: an equilibrium side, used by tests;
+ *   body_force_x  not in the paper: a uniform axial force, used by the
+ *                 pipe-flow test of the viscous source terms;
+ *   rho0 .. T0    section 2.4: the ambient gas at rest the jet enters;
+ *   hoop          the form of the hoop term of F2 (eq. 1; the source terms
+ *                 are not printed): explicit or stabilised, see above;
+ *   precision,    storage of the populations (not in the paper: every
+ *   rho_ref,      arithmetic is FP32 whatever the storage);
+ *   g_ref, layout
+ */
 typedef struct {
   uint32_t abi_version;       /* must be LBM_ABI_VERSION                      */
   int32_t nx, nr;             /* fluid nodes; >= 2 each                       */
@@ -122,12 +153,16 @@ typedef struct {
  * in lbm_create (8192 x 4096 fits, 10000 x 5000 does not). */
 int lbm_bytes_required(const lbm_config *cfg, size_t *bytes);
 
-/* Create a solver on the current HIP device, populations at the
- * equilibrium of (rho0, ux0, ur0, T0), step 0, inlet rows at the ambient
- * state (u = 0, T = T0).  lbm_create allocates the population buffers and a
- * stream itself; lbm_create_in uses dev_buf (>= lbm_bytes_required bytes,
- * 256-byte aligned) and hip_stream (a hipStream_t; NULL = default stream),
- * both owned by the caller.  *out is NULL on failure. */
+/* Create a solver on the current HIP device for the problem the paper
+ * states in sections 2.1-2.4 (the lattice, relaxation times, LES constants,
+ * property tables and edges of lbm_config), populations at the equilibrium
+ * of (rho0, ux0, ur0, T0) (the ambient state of section 2.4), step 0, inlet
+ * rows at the ambient state (u = 0, T = T0).  lbm_create allocates the
+ * population buffers and a stream itself; lbm_create_in uses dev_buf
+ * (>= lbm_bytes_required bytes, 256-byte aligned) and hip_stream (a
+ * hipStream_t; NULL = default stream), both owned by the caller.  *out is
+ * NULL on failure; LBM_EINVAL for an invalid configuration, LBM_ENOMEM when
+ * device memory runs out, LBM_EDEVICE for other HIP errors. */
 int lbm_create(const lbm_config *cfg, lbm_handle **out);
 int lbm_create_in(const lbm_config *cfg, void *dev_buf, size_t bytes,
                   void *hip_stream, lbm_handle **out);
@@ -137,20 +172,30 @@ int lbm_create_in(const lbm_config *cfg, void *dev_buf, size_t bytes,
 int lbm_set_inlet(lbm_handle *h, int32_t n_t, const double *ux, const double *ur,
                   const double *T);
 
-/* Advance n_steps >= 0 steps (eq. 1 on every node).  Enqueues only. */
+/* Advance n_steps >= 0 steps: at every node, the pull of the edge rules
+ * (section 2.4), the moments of eq. (2), the properties of eq. (6), the
+ * relaxation times of eqs. (3)-(5), the source terms and the collision of
+ * eq. (1) (section 2.1).  Enqueues only; LBM_EUNSTABLE if an earlier step
+ * was found unstable. */
 int lbm_step(lbm_handle *h, int64_t n_steps);
 
 /* Pre-collision moments (eq. 2) at the current step, each nr*nx doubles;
  * NULL pointers are skipped.  Synchronises. */
 int lbm_moments(lbm_handle *h, double *rho, double *ux, double *ur, double *T);
 
-void lbm_destroy(lbm_handle *h); /* NULL-safe; waits for queued work */
+/* Release a solver and everything the library allocated for it (not
+ * memory or a stream handed in through lbm_create_in).  NULL-safe; waits for
+ * queued work first.  Not a step of the method. */
+void lbm_destroy(lbm_handle *h);
 
 /* ---- extras ------------------------------------------------------------- */
 int64_t lbm_step_count(const lbm_handle *h); /* -1 for NULL */
 void *lbm_stream(const lbm_handle *h);       /* the handle's hipStream_t    */
 int lbm_sync(lbm_handle *h);                 /* wait; report async errors   */
-/* Group k steps into one HIP graph launch (0 disables graphs). */
+/* Group k steps into one HIP graph launch (0 disables graphs).  The graph
+ * of the handle's current tile shape is captured, instantiated and uploaded
+ * here (and again by lbm_set_tile_shape), not at the first lbm_step that
+ * replays it.  Synchronises. */
 int lbm_set_graph_steps(lbm_handle *h, int32_t k);
 /* Equilibrium fill from fields (each nr*nx); clears LBM_EUNSTABLE. */
 int lbm_set_state(lbm_handle *h, const double *rho, const double *ux,

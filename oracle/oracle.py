@@ -20,7 +20,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("LBM_REF_LIB") or os.path.join(_HERE, "liblbm_ref.so")
-SOURCES = [os.path.join(_HERE, "lbm_ref.c")]
+SOURCES = [os.path.join(_HERE, "lbm_ref.c"), os.path.join(_HERE, "lbm_ref_abi.c")]
 
 OK, EINVAL, ENOMEM, EUNSTABLE, ESTATE = 0, -1, -2, -3, -5
 BC = {"inlet": 0, "outflow": 1, "periodic": 2, "axis": 3, "freeslip": 4,

@@ -6,6 +6,7 @@ import math
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -146,3 +147,74 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2
     msg = json.loads(r.stdout.strip().splitlines()[-1])
     assert "one GPU" in msg["error"]
+
+
+# ---- the same five calls in the FP64 oracle library -----------------------
+
+@pytest.fixture(scope="module")
+def ref_abi():
+    import oracle
+    import abi
+    oracle.load()  # builds it if needed
+    return abi.load(oracle.oracle.LIB_PATH)
+
+
+def test_both_libraries_export_the_abi(lib, ref_abi):
+    """The HIP library and the oracle export the five calls of the method's
+    statement of the problem (and the state extras) under the same names,
+    so one test body can drive either."""
+    import abi
+    from paper_1002_3028_amd import lbm
+    hip = abi.load(lbm.LIB_PATH)
+    for n in abi.FIVE + abi.EXTRAS:
+        assert hasattr(hip, n), n
+        assert hasattr(ref_abi, n), n
+
+
+def _abi_case():
+    from paper_1002_3028_amd import inputs
+    p = inputs.jet_params(40, 12, cs=0.15, table_seed=0)
+    inlet = inputs.inlet_rows(12, 4.0, 0.05, 0.9, T_amb=0.1, n_t=7, noise=0.05, seed=5)
+    return p, inlet
+
+
+@pytest.mark.parametrize("case", ["jet", "closed", "annulus", "eq", "xwalls", "substrate",
+                                  "slab"])
+def test_oracle_abi_is_the_oracle(ref, ref_abi, case):
+    """Driving the oracle through the shared ABI gives bit-for-bit the result
+    of its own lbm_ref_* calls on every edge-rule case: every field of the
+    configuration (radius offset, walls and their temperatures, equilibrium
+    sides, body force, tables, hoop form) reaches the oracle where it should;
+    a shifted or dropped field would change the result."""
+    import abi
+    from gpu_common import noisy_inlet, tiny_params
+    from paper_1002_3028_amd import inputs
+    p = tiny_params(40, 12, case, hoop=1 if case != "closed" else 0)
+    inlet = noisy_inlet(12, 7, 5)
+    st = inputs.perturbed_state(40, 12, 3, r0=p["r0"])
+    codes, m = abi.run_jet(ref_abi, p, "fp64", inlet, 23, state=st)
+    assert all(v == 0 for k, v in codes.items() if k != "lbm_step_count"), codes
+    assert codes["lbm_step_count"] == 23
+    with ref.RefSolver(p) as s:
+        s.set_state(*st)
+        s.set_inlet(*inlet)
+        s.step(23)
+        mr = s.moments()
+    for k in mr:
+        np.testing.assert_array_equal(m[k], mr[k])
+
+
+@pytest.mark.parametrize("change", ["fp32", "version", "layout"])
+def test_oracle_abi_rejects_what_it_cannot_honour(ref_abi, change):
+    import abi
+    p, _ = _abi_case()
+    cfg, keep = abi.config(p, "fp32" if change == "fp32" else "fp64")
+    if change == "version":
+        cfg.abi_version = 1
+    if change == "layout":
+        cfg.layout = 2
+    h = ctypes.c_void_p(1)
+    assert ref_abi.lbm_create(ctypes.byref(cfg), ctypes.byref(h)) == -1
+    assert not h.value
+    ref_abi.lbm_destroy(None)
+    assert ref_abi.lbm_step(None, 1) == -1
