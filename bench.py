@@ -1,21 +1,30 @@
 """Benchmark of the axisymmetric D2Q9 + D2Q4 LBGK-LES step on one MI355X.
 
-A step is one time step of the whole hot path (edge pulls, moments,
-properties, Smagorinsky relaxation time, sources, collision, store) over the
-2048 x 512 jet; the FP64 conservation check runs once per 1000 steps inside
-the timed region.  Throughput is GLUPS (lattice node updates per second /
-1e9).  The roofline is HBM bandwidth at the algorithmic 104 B per node update
-for FP32 storage (13 populations read and written) and 52 B for 16-bit
-storage: `achieved` = those bytes times the node updates of one launch,
-divided by the launch duration measured with HIP events.  A launch of the
-LDS-blocked kernel performs two node updates per node while it reads and
-writes each population once; the HBM bytes it actually moves (rocprofv3
-counters) are reported beside it as `traffic`, and their rate as
-`dram_GBps`.
+A step is one time step of the whole hot path over the 2048 x 512 jet: edge
+pulls, moments, properties, Smagorinsky relaxation time, sources, collision
+and store, plus the FP64 conservation check once per 1000 steps.  The steps
+are replayed from a HIP graph captured before the warm-up.  The timed region
+(`--steps`, bracketed by device syncs) runs the check after every full 1000
+steps; a remainder of r steps is charged r/1000 of the check's measured cost.
+Throughput (`value`) is GLUPS, lattice node updates per second / 1e9, from
+that wall clock.
 
-Prints one JSON line.  Also reports FP16- and BF16-deviation storage on the
-same jet, the 4096 x 1024 jet (a working set above the 256 MB Infinity
-Cache), and the FP64 oracle timed on the host cores on a bounded sample.
+`roofline`: HBM bandwidth at the algorithmic 104 B per node update for FP32
+storage (13 populations read and written) and 52 B for 16-bit storage.
+`achieved` = those bytes times the node updates of one launch, divided by
+the launch duration, from HIP events on the solver's stream around the step
+launches of the timed region (`event_us_per_launch`).  The average duration
+of the same kernel in the committed rocprofv3 summary is given beside it
+(`rocprof_us_per_launch`).  A two-step launch updates each node twice while
+reading and writing each population once; `traffic` is the HBM bytes one
+launch moves by the rocprofv3 counters (committed summary), and
+`traffic_GBps` their rate.
+
+Prints one JSON line.  Extras: one step per launch, FP16 / BF16 / FP16SR
+storage on the same jet, the 4096 x 1024 jet (a working set above the
+256 MB Infinity Cache), the single-buffer layout, a plain copy's ceiling,
+the 64-jet batch against looped single-jet runs, the serving workload, and
+the FP64 oracle timed on the host cores on a bounded sample.
 """
 import argparse
 import json
@@ -28,6 +37,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_NODE = {"fp32": 104, "fp16": 52, "bf16": 52, "fp16sr": 52}
+CODEC = {"fp32": "CodecF32", "fp16": "CodecF16", "bf16": "CodecBF16", "fp16sr": "CodecF16SR"}
 # Vector ALU issue: 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz (a wave64 FP32
 # instruction every 4 cycles per SIMD; packed FP32 not used), lane-ops/s.
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
@@ -35,6 +45,11 @@ VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # gfx950 (eqs. 2-6 and 1 from the pulled values to the relaxed ones; the
 # counters' executed figure per kernel is read from profiles/valu_*.txt).
 VALU_COLLISION = 185
+
+
+def log(msg):
+    """Progress line on stderr (the JSON result goes to stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
 def _ensure_built():
@@ -48,22 +63,27 @@ def kernel_of(info):
     return "pair_kernel" if info["steps"] == 2 else "step_kernel"
 
 
-def read_summary(name, key):
-    """A value from a committed counter summary under profiles/, or None when
-    absent or taken on another version of the kernel source."""
+def _summary(name):
+    """key -> value of a committed summary under profiles/, or None when absent
+    or taken on another version of the kernel source."""
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     vals = {}
     for line in open(path):
-        if ":" in line and not line.startswith("#"):
+        if ":" in line and not line.startswith("#") and "|" not in line:
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
     from paper_1002_3028_amd.profsum import kernel_source_sha256
     if vals.get("kernel_source_sha256") != kernel_source_sha256():
         return None
+    return vals
+
+
+def read_summary(name, key):
+    vals = _summary(name)
     try:
-        return float(vals[key])
+        return float(vals[key]) if vals else None
     except (KeyError, ValueError):
         return None
 
@@ -73,13 +93,25 @@ def read_traffic(name):
     return read_summary(name, "hbm_bytes_per_launch")
 
 
-def alu_roofline(kernel, nodes, ms_step):
+def read_trace_us(name, kernel):
+    """Average duration (us) of the kernel whose name contains `kernel` in a
+    committed rocprofv3 --stats summary, when taken on the current source."""
+    if _summary(name) is None:
+        return None
+    for line in open(os.path.join(ROOT, "profiles", name)):
+        cols = [c.strip() for c in line.split("|")]
+        if len(cols) == 6 and kernel in cols[0]:
+            return float(cols[2])
+    return None
+
+
+def alu_roofline(kernel, prec, tag, nodes, ms_step):
     """The launch against vector-ALU issue: VALU instructions executed per
-    node update (SQ_INSTS_VALU over SQ_WAVES from the committed counter
-    summary of this kernel; null when stale) x node updates per second, and
-    the collision's own instruction count beside it."""
+    node update (SQ_INSTS_VALU over node updates / 64, from the committed
+    counter summary of this kernel; null when stale) x node updates per
+    second."""
     kind = kernel.split("_")[0]
-    executed = read_summary(f"valu_{kind}_fp32_2048x512.txt", "valu_per_node_update")
+    executed = read_summary(f"valu_{kind}_{prec}_{tag}.txt", "valu_per_node_update")
     out = {"unit": "T lane-op/s", "peak": round(VALU_PEAK_TOPS, 2),
            "valu_collision_per_node_update": VALU_COLLISION,
            "valu_executed_per_node_update": executed, "achieved": None, "frac": None}
@@ -89,34 +121,86 @@ def alu_roofline(kernel, nodes, ms_step):
     return out
 
 
-def time_jet(params, inlet, precision, steps, warmup, graph_steps=50, check_every=1000,
-             tile_shape=None, layout="two"):
-    """Returns (seconds for `steps` steps, ms per step from HIP events on the
-    solver's stream, 3-D mass from the FP64 check)."""
+def graph_group(steps, cap=50):
+    """Steps per captured graph: the largest even count <= cap that divides
+    `steps`, so that every timed step is a graph replay (cap if none)."""
+    for g in range(min(cap, steps) // 2 * 2, 1, -2):
+        if steps % g == 0:
+            return g
+    return cap
+
+
+def time_jet(params, inlet, precision, steps, warmup, check_every=1000, tile_shape=None,
+             layout="two"):
+    """Time `steps` steps of one jet, the FP64 conservation check included at
+    its cadence (once per `check_every` steps).
+
+    The graph of the timed group size is captured when the solver is set up,
+    before the warm-up; the timed region is bracketed by device syncs.  The
+    check runs inside the timed region after every full `check_every` steps;
+    a remainder of r steps is charged r / check_every of the check's cost,
+    measured beforehand (median of three).  Returns a dict: wall seconds
+    (charge included), the charge, GPU milliseconds per step from HIP events
+    on the solver's stream around the step launches only, and the group."""
     import torch
     from paper_1002_3028_amd import lbm
 
-    with lbm.Solver(params, precision, graph_steps=graph_steps, tile_shape=tile_shape,
+    g = graph_group(steps)
+    with lbm.Solver(params, precision, graph_steps=g, tile_shape=tile_shape,
                     layout=layout) as s:
         s.set_inlet(*inlet)
         s.step(warmup)
         s.sync()
+        costs = []
+        for _ in range(3):
+            t = time.perf_counter()
+            s.conservation()
+            costs.append(time.perf_counter() - t)
+        check_s = sorted(costs)[1]
         torch.cuda.synchronize()
-        ev0 = torch.cuda.Event(enable_timing=True)
-        ev1 = torch.cuda.Event(enable_timing=True)
+        evs = []
         t0 = time.perf_counter()
-        ev0.record(s.torch_stream)
         done = 0
         while done < steps:
             n = min(check_every, steps - done)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s.torch_stream)
             s.step(n)
+            e1.record(s.torch_stream)
+            evs.append((e0, e1))
             done += n
-        ev1.record(s.torch_stream)
-        mass, energy = s.conservation()  # FP64 reduction + stability check (syncs)
+            if n == check_every:
+                s.conservation()  # FP64 reduction + stability check (syncs)
+        s.sync()
         torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        ev_ms = ev0.elapsed_time(ev1)
-    return t1 - t0, ev_ms / steps, mass
+        wall = time.perf_counter() - t0
+        ev_ms = sum(a.elapsed_time(b) for a, b in evs)
+    charge = (steps % check_every) / check_every * check_s
+    return {"wall_s": wall + charge, "check_charge_s": charge, "check_s": check_s,
+            "event_ms_per_step": ev_ms / steps, "graph_steps": g}
+
+
+def roofline_block(prec, info, nodes, ms_step, traffic_name, trace_name=None, tag=None):
+    """HBM roofline of the dominant kernel: algorithmic bytes per launch over
+    the launch duration from HIP events (steps only, graph replays)."""
+    kernel = kernel_of(info)
+    ms_launch = ms_step * info["steps"]
+    updates = nodes * info["steps"]
+    alg = BYTES_PER_NODE[prec] * updates
+    achieved = alg / (ms_launch * 1e-3) / 1e9
+    traffic = read_traffic(traffic_name) if traffic_name else None
+    out = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": kernel,
+           "steps_per_launch": info["steps"], "node_updates_per_launch": updates,
+           "bytes_per_node_update": BYTES_PER_NODE[prec],
+           "algorithmic_bytes_per_launch": alg,
+           "event_us_per_launch": round(ms_launch * 1e3, 3),
+           "rocprof_us_per_launch": (read_trace_us(trace_name, f"{kernel}<lbmx::{CODEC[prec]}")
+                                     if trace_name else None),
+           "traffic_GBps": (round(traffic / (ms_launch * 1e-3) / 1e9, 1) if traffic else None)}
+    if tag:
+        out["alu"] = alu_roofline(kernel, prec, tag, nodes, ms_step)
+    return out
 
 
 def bench_batch(n_jets=64, steps=500, precision="fp32"):
@@ -161,20 +245,32 @@ def bench_batch(n_jets=64, steps=500, precision="fp32"):
             "looped_single_glups": round(nodes * steps / t_loop / 1e9, 3)}
 
 
-def bench_serving(n_requests=200, precision="fp16"):
-    """Poisson trace (seed 3): capacity with every request admitted at once,
-    then p50/p99 latency at 0.7 x that rate."""
+def bench_serving(n_requests=2000):
+    """The serving workload (Poisson trace of seed 3): saturated capacity of
+    FP32 and FP16 storage (every request admitted at once), then both
+    storages on the same trace at one arrival rate, 0.7 x the FP32
+    capacity: p50/p99 latency (arrival to completion) and throughput."""
     from paper_1002_3028_amd import inputs, serve
 
-    cap, _ = serve.serve(inputs.arrival_trace(n_requests, 3, rate=1.0), precision,
-                         16 << 30, 256, 100, realtime=False)
-    rate = 0.7 * cap["requests_per_s"]
-    run, _ = serve.serve(inputs.arrival_trace(n_requests, 3, rate=rate), precision,
-                         16 << 30, 256, 100, realtime=True)
-    return {"requests": n_requests, "precision": precision,
-            "capacity_req_per_s": cap["requests_per_s"], "capacity_glups": cap["glups"],
-            "rate_req_per_s": round(rate, 3), "p50_s": run["p50_s"], "p99_s": run["p99_s"],
-            "glups_at_rate": run["glups"]}
+    out = {"requests": n_requests, "trace_seed": 3}
+    cap = {}
+    for prec in ("fp32", "fp16"):
+        log(f"serving {prec}: capacity, {n_requests} requests")
+        c, _ = serve.serve(inputs.arrival_trace(n_requests, 3, rate=1.0), prec,
+                           16 << 30, 256, 100, realtime=False)
+        cap[prec] = c
+        out[f"{prec}_capacity_req_per_s"] = c["requests_per_s"]
+        out[f"{prec}_capacity_glups"] = c["glups"]
+    rate = 0.7 * cap["fp32"]["requests_per_s"]
+    out["rate_req_per_s"] = round(rate, 3)
+    trace = inputs.arrival_trace(n_requests, 3, rate=rate)
+    for prec in ("fp32", "fp16"):
+        log(f"serving {prec}: {rate:.1f} requests/s")
+        run, _ = serve.serve(trace, prec, 16 << 30, 256, 100, realtime=True)
+        out[prec] = {"p50_s": run["p50_s"], "p99_s": run["p99_s"], "mean_s": run["mean_s"],
+                     "served_req_per_s": run["requests_per_s"], "glups": run["glups"],
+                     "peak_slots": run["peak_slots"]}
+    return out
 
 
 def copy_ceiling(nbytes, reps=50):
@@ -202,7 +298,19 @@ def copy_ceiling(nbytes, reps=50):
             "frac_of_peak": round(2 * nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            return next((ln.split(":", 1)[1].strip() for ln in fh
+                         if ln.startswith("model name")), "")
+    except OSError:
+        return ""
+
+
 def cpu_baseline(params, inlet, budget_s=12.0):
+    """The FP64 oracle as it stands on the host cores (OpenMP over radial
+    rows), on a bounded sample of the same jet: the steps that fit about
+    budget_s after two warm steps."""
     import oracle
 
     threads = max(1, min(16, os.cpu_count() or 1))
@@ -219,7 +327,8 @@ def cpu_baseline(params, inlet, budget_s=12.0):
     return {"value": round(nodes * n / dt / 1e9, 6), "unit": "GLUPS", "cores": threads,
             "kind": "oracle",
             "sample": f"{params['nx']}x{params['nr']} jet, steps 2..{n + 2} from rest "
-                      f"(FP64, OpenMP over radial rows), {dt:.1f} s"}
+                      f"(FP64, OpenMP over radial rows), {dt:.1f} s",
+            "cpu": _cpu_model(), "compiler": "gcc -O2 -std=c11 -ffp-contract=off -fopenmp"}
 
 
 def oracle_timing():
@@ -232,13 +341,7 @@ def oracle_timing():
     import oracle
     from paper_1002_3028_amd import inputs
 
-    model = ""
-    try:
-        with open("/proc/cpuinfo") as fh:
-            model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")),
-                         "")
-    except OSError:
-        pass
+    model = _cpu_model()
     cores = max(1, min(16, os.cpu_count() or 1))
     cases = [("128x32 jet, 500 steps", inputs.workload_small()[:2], 500),
              ("2048x512 jet, first 200 steps", inputs.workload_single(n_t=200)[:2], 200),
@@ -273,6 +376,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=500)
     ap.add_argument("--no-extra", action="store_true", help="headline workload only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle baseline")
+    ap.add_argument("--batch-steps", type=int, default=5000,
+                    help="steps of the 64-jet batch leg")
+    ap.add_argument("--serving-requests", type=int, default=2000,
+                    help="requests of the serving leg")
     ap.add_argument("--oracle-timing", action="store_true",
                     help="only time the FP64 oracle (1 thread and all cores) and exit")
     args = ap.parse_args()
@@ -296,13 +403,9 @@ def main():
     nodes = nx * nr
     shape = autotune.best_shape(p, inlet, "fp32")
     info = lbm.tile_shape_info(shape)
-    wall, ms_step, _ = time_jet(p, inlet, "fp32", args.steps, args.warmup, tile_shape=shape)
-    glups = nodes * args.steps / wall / 1e9
-    ms_launch = ms_step * info["steps"]
-    updates_per_launch = nodes * info["steps"]
-    alg_bytes = BYTES_PER_NODE["fp32"] * updates_per_launch
-    achieved = alg_bytes / (ms_launch * 1e-3) / 1e9
-    traffic = read_traffic(f"traffic_{kernel_of(info).split('_')[0]}_fp32_2048x512.txt")
+    log(f"headline: 2048x512 fp32, shape {shape}, {args.steps} steps")
+    t = time_jet(p, inlet, "fp32", args.steps, args.warmup, tile_shape=shape)
+    glups = nodes * args.steps / t["wall_s"] / 1e9
     line = {
         "metric": "GLUPS & % HBM peak, FP32 vs FP16-storage; batched-jet p50/p99 solve latency",
         "value": round(glups, 3),
@@ -310,7 +413,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(wall / args.steps * 1e3, 5),
+        "ms_per_step": round(t["wall_s"] / args.steps * 1e3, 5),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -319,63 +422,72 @@ def main():
         "config": {"workload": "single axisymmetric jet, 2048 axial x 512 radial nodes, FP32 "
                                "populations, parabolic inlet R=32 U_max=0.08 with 1% noise, "
                                "T_in=1, C_s=0.17, tau=0.6, property tables seed 1",
-                   "nx": nx, "nr": nr, "precision": "fp32", "graph_steps": 50,
+                   "nx": nx, "nr": nr, "precision": "fp32", "graph_steps": t["graph_steps"],
+                   "fp64_check_every": 1000,
+                   "fp64_check_charged_s": round(t["check_charge_s"], 7),
                    "tile_shape": info},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "kernel": kernel_of(info),
-                     "steps_per_launch": info["steps"],
-                     "node_updates_per_launch": updates_per_launch,
-                     "bytes_per_node_update": BYTES_PER_NODE["fp32"],
-                     "algorithmic_bytes_per_launch": alg_bytes,
-                     "kernel_ms_per_launch": round(ms_launch, 5),
-                     "dram_GBps": (round(traffic / (ms_launch * 1e-3) / 1e9, 1)
-                                   if traffic else None),
-                     "alu": alu_roofline(kernel_of(info), nodes, ms_step)},
+        "roofline": roofline_block("fp32", info, nodes, t["event_ms_per_step"],
+                                   f"traffic_{kernel_of(info).split('_')[0]}_fp32_2048x512.txt",
+                                   "pair_kernel_fp32_2048x512_kernel_trace.txt", tag="2048x512"),
     }
     if not args.no_extra:
         extra = {}
         steps_x = max(200, args.steps // 4)
+        warm_x = max(10, args.warmup // 2)
 
-        def entry(prec, q, w, ms, n_nodes, n_steps):
-            # ms: per step; algorithmic bytes per node update over the step time
+        def entry(prec, q, t, n_nodes, n_steps, traffic_name=None, trace_name=None):
             inf = lbm.tile_shape_info(q)
-            return {"glups": round(n_nodes * n_steps / w / 1e9, 3), "tile_shape": inf,
-                    "hbm_frac": round(BYTES_PER_NODE[prec] * n_nodes /
-                                      (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            e = {"glups": round(n_nodes * n_steps / t["wall_s"] / 1e9, 3), "tile_shape": inf,
+                 "event_glups": round(n_nodes / (t["event_ms_per_step"] * 1e-3) / 1e9, 3)}
+            e["roofline"] = roofline_block(prec, inf, n_nodes, t["event_ms_per_step"],
+                                           traffic_name, trace_name)
+            return e
 
         # the same jet with one step per launch (the best one-step shape)
         q1 = autotune.best_shape(p, inlet, "fp32", steps=1)
-        w, ms, _ = time_jet(p, inlet, "fp32", steps_x, args.warmup // 2, tile_shape=q1)
-        extra["fp32_2048x512_one_step"] = entry("fp32", q1, w, ms, nodes, steps_x)
+        tt = time_jet(p, inlet, "fp32", steps_x, warm_x, tile_shape=q1)
+        extra["fp32_2048x512_one_step"] = entry("fp32", q1, tt, nodes, steps_x,
+                                                "traffic_step_fp32_2048x512.txt")
         for prec in ("fp16", "bf16", "fp16sr"):
             q = autotune.best_shape(p, inlet, prec)
-            w, ms, _ = time_jet(p, inlet, prec, steps_x, args.warmup // 2, tile_shape=q)
-            extra[f"{prec}_2048x512"] = entry(prec, q, w, ms, nodes, steps_x)
+            log(f"2048x512 {prec}, shape {q}")
+            tt = time_jet(p, inlet, prec, steps_x, warm_x, tile_shape=q)
+            kind = kernel_of(lbm.tile_shape_info(q)).split("_")[0]
+            extra[f"{prec}_2048x512"] = entry(prec, q, tt, nodes, steps_x,
+                                              f"traffic_{kind}_{prec}_2048x512.txt")
+        # the 4096 x 1024 jet: its FP32 buffers (436 MB) exceed the Infinity
+        # Cache, so this is the HBM-bandwidth case
         pl, inl, _ = inputs.workload_large(n_t=4000)
         nodes_l = pl["nx"] * pl["nr"]
         steps_l = max(100, args.steps // 10)
         for prec in ("fp32", "fp16", "fp16sr"):
             q = autotune.best_shape(pl, inl, prec)
-            w, ms, _ = time_jet(pl, inl, prec, steps_l, 100, tile_shape=q)
-            extra[f"{prec}_4096x1024"] = entry(prec, q, w, ms, nodes_l, steps_l)
+            log(f"4096x1024 {prec}, shape {q}")
+            tt = time_jet(pl, inl, prec, steps_l, warm_x, tile_shape=q)
+            kind = kernel_of(lbm.tile_shape_info(q)).split("_")[0]
+            extra[f"{prec}_4096x1024"] = entry(prec, q, tt, nodes_l, steps_l,
+                                               f"traffic_{kind}_{prec}_4096x1024.txt",
+                                               f"{kind}_kernel_{prec}_4096x1024_kernel_trace.txt")
         # one buffer updated in place (half the memory, one step per launch)
         for tag, (pp, ii, nn, ss) in (("2048x512", (p, inlet, nodes, steps_x)),
                                       ("4096x1024", (pl, inl, nodes_l, steps_l))):
-            w, ms, _ = time_jet(pp, ii, "fp32", ss, 100, layout="single")
+            tt = time_jet(pp, ii, "fp32", ss, warm_x, layout="single")
             extra[f"fp32_{tag}_single_buffer"] = {
-                "glups": round(nn * ss / w / 1e9, 3),
+                "glups": round(nn * ss / tt["wall_s"] / 1e9, 3),
                 "bytes": lbm.bytes_required(pp, "fp32", "single"),
                 "two_buffer_bytes": lbm.bytes_required(pp, "fp32", "two"),
-                "hbm_frac": round(BYTES_PER_NODE["fp32"] * nn / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+                "hbm_frac": round(BYTES_PER_NODE["fp32"] * nn / (tt["event_ms_per_step"] * 1e-3)
+                                  / 1e9 / HBM_PEAK_GBS, 4)}
         # practical streaming ceiling: a plain copy of each jet's two-buffer footprint
         extra["copy_kernel"] = {tag: copy_ceiling(lbm.bytes_required(pp, "fp32", "two") // 2)
                                 for tag, pp in (("2048x512_fp32", p), ("4096x1024_fp32", pl))}
-        extra["batch_64_jets"] = bench_batch()
-        extra["serving_fp16"] = bench_serving(precision="fp16")
-        extra["serving_fp32"] = bench_serving(precision="fp32")
+        log("64-jet batch")
+        extra["batch_64_jets"] = bench_batch(steps=args.batch_steps)
+        log("serving")
+        extra["serving"] = bench_serving(args.serving_requests)
         line["extra"] = extra
     if not args.no_cpu:
+        log("oracle on the host cores")
         line["cpu_baseline"] = cpu_baseline(p, inlet)
     print(json.dumps(line), flush=True)
 

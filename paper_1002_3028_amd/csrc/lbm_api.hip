@@ -57,7 +57,7 @@ int upload_desc(lbm_handle *h) {
 
 int set_shape(lbm_handle *h, int shape) {
   int n;
-  const TileShape *ts = tile_shapes(&n);
+  tile_shapes(&n);
   if (shape < 0 || shape >= n) return LBM_EINVAL;
   if (h->layout == LBM_LAYOUT_SINGLE && shape != 0) return LBM_EINVAL;
   int32_t tx;
@@ -261,6 +261,21 @@ int capture_group(lbm_handle *h, int32_t k, bool pair) {
   return LBM_OK;
 }
 
+// Capture and upload the graph of the handle's group size and shape now, so
+// that the first lbm_step that replays it pays no capture or instantiation.
+int prepare_graph(lbm_handle *h) {
+  if (h->graph_k <= 0) return LBM_OK;
+  if (h->gexec && h->gexec_k == h->graph_k && h->gexec_shape == h->shape) return LBM_OK;
+  drop_graph(h);
+  int nsh;
+  const int rc = capture_group(h, h->graph_k, tile_shapes(&nsh)[h->shape].steps == 2);
+  if (rc) return rc;
+  // (an optimisation only: the graph also uploads itself at its first launch)
+  (void)hipGraphUpload(h->gexec, h->stream);
+  LBM_HIP(hipStreamSynchronize(h->stream));
+  return LBM_OK;
+}
+
 int launch_steps(lbm_handle *h, int64_t n) {
   int nsh;
   const bool pair = tile_shapes(&nsh)[h->shape].steps == 2;
@@ -358,7 +373,7 @@ int lbm_set_graph_steps(lbm_handle *h, int32_t k) {
   LBM_HIP(hipStreamSynchronize(h->stream));
   h->graph_k = k;
   if (k == 0) drop_graph(h);
-  return LBM_OK;
+  return prepare_graph(h);
 }
 
 int lbm_set_tile_shape(lbm_handle *h, int32_t index) {
@@ -368,7 +383,7 @@ int lbm_set_tile_shape(lbm_handle *h, int32_t index) {
   h->base = h->step;
   const int rc = set_shape(h, index);
   drop_graph(h);
-  return rc;
+  return rc ? rc : prepare_graph(h);
 }
 
 int lbm_moments(lbm_handle *h, double *rho, double *ux, double *ur, double *T) {

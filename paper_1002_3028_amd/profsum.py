@@ -8,8 +8,8 @@
            run of SQ_INSTS_VALU and SQ_WAVES (one instruction of a wave
            serves 64 lanes, so per update = total / (updates / 64)).
 
-Both write a short text file that records the command which produced the
-counters and, for traffic, the SHA-256 of the kernel sources it was taken on.
+Each writes a short text file that records the command which produced the
+figures and the SHA-256 of the kernel sources they were taken on.
 """
 from __future__ import annotations
 
@@ -48,6 +48,7 @@ def stats(args):
         lines.append(f"{name} | {r['Calls']} | {float(r['AverageNs']) / 1e3:.3f} | "
                      f"{float(r['MinNs']) / 1e3:.3f} | {float(r['MaxNs']) / 1e3:.3f} | "
                      f"{float(r['Percentage']):.2f}")
+    lines.append(f"kernel_source_sha256: {kernel_source_sha256()}")
     with open(args.out, "w") as fh:
         fh.write("\n".join(lines) + "\n")
 

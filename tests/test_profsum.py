@@ -81,3 +81,39 @@ def test_bench_reads_only_current_summaries(tmp_path, monkeypatch):
     assert bench.read_traffic("x.txt") == 123.0
     assert bench.read_traffic("y.txt") is None
     assert bench.read_traffic("missing.txt") is None
+
+
+def test_bench_reads_kernel_average_from_stats(tmp_path, monkeypatch):
+    """A --stats summary written by profsum gives bench.py the average
+    duration of the named kernel, and nothing once the sources change."""
+    import bench
+    rows = [{"Name": "void lbmx::pair_kernel<lbmx::CodecF32, 8, 4, 5, 8>(x)", "Calls": "10",
+             "AverageNs": "27263.0", "MinNs": "26000", "MaxNs": "28000", "Percentage": "90"},
+            {"Name": "lbmx::advance_kernel(x)", "Calls": "1", "AverageNs": "1500.0",
+             "MinNs": "1500", "MaxNs": "1500", "Percentage": "10"}]
+    path = tmp_path / "s.csv"
+    with open(path, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=list(rows[0]))
+        w.writeheader()
+        w.writerows(rows)
+    prof = tmp_path / "profiles"
+    prof.mkdir()
+    _run(["stats", "--csv", str(path), "--out", str(prof / "k.txt"), "--title", "t",
+          "--command", "c"])
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.read_trace_us("k.txt", "pair_kernel<lbmx::CodecF32") == pytest.approx(27.263)
+    assert bench.read_trace_us("k.txt", "pair_kernel<lbmx::CodecF16") is None
+    text = (prof / "k.txt").read_text().replace("kernel_source_sha256: ", "kernel_source_sha256: 0")
+    (prof / "k.txt").write_text(text)
+    assert bench.read_trace_us("k.txt", "pair_kernel<lbmx::CodecF32") is None
+
+
+@pytest.mark.parametrize("steps,group", [(20, 20), (20000, 50), (2000, 50), (200, 50),
+                                         (30, 30), (42, 42), (5, 50), (98, 14)])
+def test_bench_graph_group_divides_the_timed_steps(steps, group):
+    """Every timed step is a replay of the graph captured before the clock
+    starts: the group is the largest even divisor up to 50."""
+    import bench
+    g = bench.graph_group(steps)
+    assert g == group
+    assert g % 2 == 0 and (steps % g == 0 or g == 50)
