@@ -1,18 +1,23 @@
-"""Time-averaged profiles over steps [10 000, 20 000] of a 20 000-step run,
-sampled every 50 steps (centreline u_x(x), T(x) and radial u_x(r), T(r) at
-i = nx/2 and nx-1; profile error ||d||_2 / ||ref||_2 per quantity), for the
-2048 x 512 jet (the benchmark's workload) and the 1024 x 256 twin of the
-4096 x 1024 jet, against the FP64 oracle.
+"""Second tier of GPU-vs-oracle parity on the benchmark's own jet: time
+averages over steps [10 000, 20 000] of a 20 000-step run, sampled every 50
+steps, of the centreline u_x(x), T(x) and the radial u_x(r), T(r) at
+i = nx/2 and i = nx - 1; profile error ||d||_2 / ||ref||_2 per quantity over
+all sampled points.  The oracle's averages are stored in tests/golden/
+(written by tests/golden/make_long_profiles.py, which calls only the
+oracle), so the GPU side takes seconds.
 
-A chaotic LES jet makes such averages noisy: the same FP32 run with its inlet
-rows perturbed by 1e-6 (relative) differs from itself by the realization
-floor.  A storage form passes if each error is within max(1 %, 1.5 x floor).
-FP16 storage rounds the temperature
-populations with a bias that moves T far past the floor (an expected
-failure that reports its numbers); stochastic rounding (fp16sr) removes it.
+2048 x 512 jet (the benchmark's workload): FP32 and FP16 with stochastic
+rounding must stay within 1 %, the method's bound for time-averaged
+profiles.  FP16 and BF16 with round-to-nearest bias the temperature over
+such runs; their cases are expected failures that report their numbers.
 
-The oracle needs about four minutes of 16 host cores for the 26 G node
-updates, so the tests run only when LBM_LONG_TESTS=1 is set."""
+1024 x 256 twin of the 4096 x 1024 jet: a smaller jet whose 10 000-step
+averages are much noisier.  The realization spread is measured as the
+distance between the FP32 run and three FP32 runs whose inlet rows of u_x and
+T are scaled by 1 + 1e-6 N(0, 1) (three seeds; the perturbation enters at
+every step, so rounding cannot erase it before the jet forms).  Each storage
+form must stay within max(1 %, the largest of the three spreads)."""
+import importlib.util
 import json
 import os
 import time
@@ -20,103 +25,112 @@ import time
 import numpy as np
 import pytest
 
-from gpu_common import host_threads, require_gpu
+from gpu_common import require_gpu
 
-pytestmark = [pytest.mark.gpu, pytest.mark.slow,
-              pytest.mark.skipif(os.environ.get("LBM_LONG_TESTS") != "1",
-                                 reason="about 4 minutes of FP64 oracle; set LBM_LONG_TESTS=1")]
+pytestmark = pytest.mark.gpu
 
+HERE = os.path.dirname(os.path.abspath(__file__))
 N_STEPS, EVERY, CHUNK = 20000, 50, 1000
+PERTURB_SEEDS = (7, 8, 9)
 
 
-def _sample(m):
-    nx = m["ux"].shape[1]
-    return {"ux": np.concatenate([m["ux"][0], m["ux"][:, nx // 2], m["ux"][:, -1]]),
-            "T": np.concatenate([m["T"][0], m["T"][:, nx // 2], m["T"][:, -1]])}
+def _golden():
+    spec = importlib.util.spec_from_file_location(
+        "make_long_profiles", os.path.join(HERE, "golden", "make_long_profiles.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
 
 
-def _averaged(solver, name):
-    t0 = time.time()
-    for q in range(N_STEPS // 2 // CHUNK):
-        solver.step(CHUNK)
-        print(f"{name}: step {(q + 1) * CHUNK}, {time.time() - t0:.0f} s", flush=True)
-    acc, n = {"ux": 0.0, "T": 0.0}, 0
-    for q in range(N_STEPS // 2 // EVERY + 1):
-        s = _sample(solver.moments())
-        acc = {k: acc[k] + s[k] for k in acc}
-        n += 1
-        if q < N_STEPS // 2 // EVERY:
-            solver.step(EVERY)
-        if q % (CHUNK // EVERY) == 0:
-            print(f"{name}: step {N_STEPS // 2 + q * EVERY}, {time.time() - t0:.0f} s", flush=True)
-    return {k: v / n for k, v in acc.items()}
+def _quantities(prof):
+    return {"ux": np.concatenate([prof["ux_axis"], prof["ux_mid"], prof["ux_exit"]]),
+            "T": np.concatenate([prof["T_axis"], prof["T_mid"], prof["T_exit"]])}
 
 
 def _err(a, b):
+    a, b = _quantities(a), _quantities(b)
     return {k: float(np.linalg.norm(a[k] - b[k]) / np.linalg.norm(b[k])) for k in b}
 
 
-def _gpu_run(p, inlet, precision, perturb=0.0):
-    """perturb > 0 scales the inlet rows of u_x and T by 1 + perturb N(0, 1).
-    The perturbation enters at every step, so rounding cannot erase it before
-    the jet forms, as it can erase one of the initial rest state."""
+def _gpu_run(gold, p, inlet, precision, perturb_seed=None):
+    """The oracle's procedure (gold.averaged) on the GPU solver."""
     from paper_1002_3028_amd import lbm
-    if perturb:
-        rng = np.random.default_rng(7)
+    if perturb_seed is not None:
+        rng = np.random.default_rng(perturb_seed)
         ux, ur, T = (np.asarray(a, dtype=np.float64) for a in inlet)
-        inlet = (ux * (1.0 + perturb * rng.standard_normal(ux.shape)), ur,
-                 T * (1.0 + perturb * rng.standard_normal(T.shape)))
+        inlet = (ux * (1.0 + 1e-6 * rng.standard_normal(ux.shape)), ur,
+                 T * (1.0 + 1e-6 * rng.standard_normal(T.shape)))
+    t0 = time.time()
     with lbm.Solver(p, precision, graph_steps=EVERY) as s:
         s.set_inlet(*inlet)
-        return _averaged(s, precision + (" perturbed" if perturb else ""))
+        out = gold.averaged(s, f"{precision} {p['nx']}x{p['nr']}")
+    print(f"{precision} {p['nx']}x{p['nr']} perturb={perturb_seed}: {time.time() - t0:.1f} s",
+          flush=True)
+    return out
 
 
-def _reference(p, inlet, name):
+@pytest.fixture(scope="module")
+def gold():
     require_gpu()
-    import oracle
-    with oracle.RefSolver(p, threads=host_threads()) as r:
-        r.set_inlet(*inlet)
-        ref = _averaged(r, f"oracle {name}")
-    floor = _err(_gpu_run(p, inlet, "fp32", 1e-6), _gpu_run(p, inlet, "fp32"))
-    print(json.dumps({"grid": name, "realization_floor": floor}), flush=True)
-    return p, inlet, ref, floor
+    return _golden()
+
+
+def _case(gold, name):
+    p, inlet = gold.jets()[name]
+    ref = gold.read(os.path.join(HERE, "golden", f"long_profiles_{name}.txt"))
+    return p, inlet, ref
 
 
 @pytest.fixture(scope="module")
-def headline():
-    from paper_1002_3028_amd import inputs
-    p, inlet, _ = inputs.workload_single(n_t=N_STEPS)
-    return _reference(p, inlet, "2048x512")
+def headline(gold):
+    return _case(gold, "2048x512")
 
 
 @pytest.fixture(scope="module")
-def twin():
-    from paper_1002_3028_amd import inputs
-    p, inlet, _ = inputs.workload_large(nx=1024, nr=256, n_t=N_STEPS)
-    return _reference(p, inlet, "1024x256")
-
-
-def _check(case, precision):
-    p, inlet, ref, floor = case
-    err = _err(_gpu_run(p, inlet, precision), ref)
-    print(json.dumps({"grid": f"{p['nx']}x{p['nr']}", "steps": N_STEPS, "precision": precision,
-                      "profile_error": err, "floor": floor}), flush=True)
-    for k in err:
-        assert err[k] < max(1e-2, 1.5 * floor[k]), (k, err[k], floor[k])
+def twin(gold):
+    p, inlet, ref = _case(gold, "1024x256")
+    base = _gpu_run(gold, p, inlet, "fp32")
+    spread = [_err(_gpu_run(gold, p, inlet, "fp32", s), base) for s in PERTURB_SEEDS]
+    floor = {k: max(d[k] for d in spread) for k in ("ux", "T")}
+    print(json.dumps({"grid": "1024x256", "realization_spread": spread, "floor": floor}),
+          flush=True)
+    return p, inlet, ref, floor, base
 
 
 FP16_BIAS = pytest.mark.xfail(
-    reason="FP16 storage biases T over 20 000 steps (2.8e-2 / 3.5e-2 measured, floor ~3e-3)",
-    strict=False)
-BF16_BIAS = pytest.mark.xfail(reason="BF16 storage: 6.2e-2 u_x / 0.21 T measured", strict=False)
+    reason="round-to-nearest FP16 storage biases T over 20 000 steps", strict=False)
+BF16_BIAS = pytest.mark.xfail(reason="BF16 storage: 8 significant bits", strict=False)
 
 
-@pytest.mark.parametrize("precision", ["fp32", pytest.param("fp16", marks=FP16_BIAS), "fp16sr"])
-def test_headline_jet_time_averaged_profiles(headline, precision):
-    _check(headline, precision)
+@pytest.mark.parametrize("precision", ["fp32", "fp16sr", pytest.param("fp16", marks=FP16_BIAS),
+                                       pytest.param("bf16", marks=BF16_BIAS)])
+def test_headline_jet_time_averaged_profiles(gold, headline, precision):
+    p, inlet, ref = headline
+    err = _err(_gpu_run(gold, p, inlet, precision), ref)
+    print(json.dumps({"grid": "2048x512", "steps": N_STEPS, "precision": precision,
+                      "profile_error": err}), flush=True)
+    for k in err:
+        assert err[k] < 1e-2, (k, err[k])
 
 
-@pytest.mark.parametrize("precision", ["fp32", pytest.param("fp16", marks=FP16_BIAS),
-                                       pytest.param("bf16", marks=BF16_BIAS), "fp16sr"])
-def test_twin_time_averaged_profiles(twin, precision):
-    _check(twin, precision)
+def test_headline_jet_realization_spread(gold, headline):
+    """Reported beside the errors: how far one FP32 realization of the
+    benchmark jet's averages moves under a 1e-6 inlet perturbation."""
+    p, inlet, ref = headline
+    base = _gpu_run(gold, p, inlet, "fp32")
+    spread = [_err(_gpu_run(gold, p, inlet, "fp32", s), base) for s in PERTURB_SEEDS[:2]]
+    print(json.dumps({"grid": "2048x512", "realization_spread": spread}), flush=True)
+    assert all(d[k] < 1e-2 for d in spread for k in d)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp16sr", pytest.param("fp16", marks=FP16_BIAS),
+                                       pytest.param("bf16", marks=BF16_BIAS)])
+def test_twin_time_averaged_profiles(gold, twin, precision):
+    p, inlet, ref, floor, base = twin
+    got = base if precision == "fp32" else _gpu_run(gold, p, inlet, precision)
+    err = _err(got, ref)
+    print(json.dumps({"grid": "1024x256", "steps": N_STEPS, "precision": precision,
+                      "profile_error": err, "floor": floor,
+                      "vs_fp32": _err(got, base) if precision != "fp32" else None}), flush=True)
+    for k in err:
+        assert err[k] < max(1e-2, floor[k]), (k, err[k], floor[k])
