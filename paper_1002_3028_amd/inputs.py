@@ -119,6 +119,27 @@ def workload_large(nx: int = 4096, nr: int = 1024, n_t: int = 20000, hoop: int =
     return p, inlet, 20000
 
 
+def workload_substrate(nx: int = 2048, nr: int = 512, n_t: int = 20000, T_wall: float = 0.0,
+                       hoop: int = 1):
+    """The 2048 x 512 jet impinging on a substrate (the paper's second case,
+    section 4.2): physics and inlet of workload_single, with a no-slip wall at
+    x = nx (the target plane) held at T_wall in place of the outflow.  The
+    initial state is a formed jet column: along the whole axis the inlet
+    profile u_x = U_max (1 - (r/R)^2), T = T_in for r < R, ambient outside,
+    so that the column meets the plate at once (from rest the jet would need
+    some 25 000 steps to cross 2048 nodes).  Returns (params, inlet, state)
+    with state = (rho, ux, ur, T), each (nr, nx)."""
+    p = jet_params(nx, nr, cs=0.17, table_seed=1, hoop=hoop)
+    p["bc"] = ("inlet", "wall", "axis", "freeslip")
+    p["wall_T"] = [math.nan, T_wall, math.nan, math.nan]
+    radius = nr / 16.0
+    inlet = inlet_rows(nr, radius, 0.08, 1.0, n_t=n_t, noise=0.01, seed=1)
+    col_u, _, col_T = inlet_rows(nr, radius, 0.08, 1.0)
+    ux = np.tile(col_u[0][:, None], (1, nx))
+    T = np.tile(col_T[0][:, None], (1, nx))
+    return p, inlet, (np.ones((nr, nx)), ux, np.zeros((nr, nx)), T)
+
+
 def batch_jets(n: int = 64, seed: int = 2, steps: int = 5000, hoop: int = 1):
     """n independent jets of uneven sizes: nx in {256..2048 step 128}, nr in
     {64..512 step 32}, inlet radius nr/16, U_max ~ U[0.03, 0.1],
