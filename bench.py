@@ -171,9 +171,9 @@ def time_jet(params, inlet, precision, steps, warmup, check_every=1000, tile_sha
             done += n
             if n == check_every:
                 s.conservation()  # FP64 reduction + stability check (syncs)
-        s.sync()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
+        s.sync()  # the solver's own stability flag, read outside the clock
         ev_ms = sum(a.elapsed_time(b) for a, b in evs)
     charge = (steps % check_every) / check_every * check_s
     return {"wall_s": wall + charge, "check_charge_s": charge, "check_s": check_s,
@@ -203,26 +203,41 @@ def roofline_block(prec, info, nodes, ms_step, traffic_name, trace_name=None, ta
     return out
 
 
-def bench_batch(n_jets=64, steps=500, precision="fp32"):
-    """64 jets of uneven sizes (seed 2) advanced together in one persistent
-    launch per step, against the same jets run one after another through the
-    single-jet path (same kernel).  Aggregate GLUPS of both."""
+def bench_batch(n_jets=64, steps=5000, precision="fp32"):
+    """64 jets of uneven sizes (seed 2) advanced together, one persistent
+    launch per step (or pair of steps) per cohort, with the launch
+    configuration the batch tuner picks for this set (tile shape, grid,
+    cohort size, streams; tuned once and cached) and, for comparison, with
+    the batch's defaults; against the same jets run one after another
+    through the single-jet path.  Aggregate GLUPS of each."""
     import torch
-    from paper_1002_3028_amd import inputs, lbm
+    from paper_1002_3028_amd import autotune, inputs, lbm
 
     jets = inputs.batch_jets(n_jets, seed=2, steps=steps)
     nodes = sum(p["nx"] * p["nr"] for p, _, _ in jets)
     budget = sum(lbm.bytes_required(p, precision) for p, _, _ in jets) + (64 << 20)
-    with lbm.Batch(budget, n_jets, precision) as b:
-        for p, inlet, _ in jets:
-            b.admit(p, inlet, steps + 100)
-        b.run(50)
-        b.sync()
-        t0 = time.perf_counter()
-        for _ in range(steps // 50):
+    tuned = autotune.tune_batch([(p, inlet) for p, inlet, _ in jets], precision)
+    groups = steps // 50
+
+    def batched(cfg):
+        with lbm.Batch(budget, n_jets, precision) as b:
+            if cfg is not None:
+                autotune.apply_batch(b, cfg)
+            for p, inlet, _ in jets:
+                b.admit(p, inlet, steps + 100)
             b.run(50)
-        b.sync()
-        t_batch = time.perf_counter() - t0
+            b.sync()
+            t0 = time.perf_counter()
+            for _ in range(groups):
+                b.run(50)
+            b.sync()
+            return nodes * groups * 50 / (time.perf_counter() - t0) / 1e9
+
+    out = {"jets": n_jets, "nodes": nodes, "steps": groups * 50, "precision": precision,
+           "tuned": {k: tuned[k] for k in ("shape", "workgroups", "cohort_mib", "streams")},
+           "tuned_shape": lbm.tile_shape_info(tuned["shape"]),
+           "batched_glups": round(batched(tuned), 3),
+           "batched_default_glups": round(batched(None), 3)}
     solvers = []
     for p, inlet, _ in jets:
         s = lbm.Solver(p, precision, graph_steps=50)
@@ -239,10 +254,8 @@ def bench_batch(n_jets=64, steps=500, precision="fp32"):
     t_loop = time.perf_counter() - t0
     for s in solvers:
         s.close()
-    upd = nodes * (steps // 50) * 50
-    return {"jets": n_jets, "nodes": nodes, "steps": (steps // 50) * 50, "precision": precision,
-            "batched_glups": round(upd / t_batch / 1e9, 3),
-            "looped_single_glups": round(nodes * steps / t_loop / 1e9, 3)}
+    out["looped_single_glups"] = round(nodes * steps / t_loop / 1e9, 3)
+    return out
 
 
 def bench_serving(n_requests=2000):

@@ -1,12 +1,16 @@
-"""Launch-shape autotuner for the step kernel.
+"""Launch autotuner of the step kernels.
 
-For a precision and a size class it times every compiled tile shape (block
-shape, nodes per lane, cache policy, one or two steps per launch) on a
-representative jet and keeps the fastest.  Results are cached as JSON keyed by (GPU architecture, precision,
-size class) in $LBM_AUTOTUNE_CACHE or ~/.cache/lbmx/autotune.json.
+Single jets (best_shape): for a precision and a size class it times every
+compiled tile shape (block shape, nodes per lane, cache policy, one or two
+steps per launch) on a representative jet and keeps the fastest.  Size
+classes follow the memory system: the two population buffers either fit the
+256 MB Infinity Cache with room to spare, or do not.
 
-Size classes follow the memory system: the two population buffers either
-fit the 256 MB Infinity Cache with room to spare, or do not.
+Batches (tune_batch): for a set of jets advanced together it searches the
+tile shape, the persistent grid, the cohort size and the number of streams.
+
+Results are cached as JSON keyed by GPU architecture, precision and size
+class in $LBM_AUTOTUNE_CACHE or ~/.cache/lbmx/autotune.json.
 """
 from __future__ import annotations
 
@@ -107,25 +111,93 @@ def best_shape(params: dict, inlet, precision: str, retune: bool = False,
     return q
 
 
-def tune_batch(jets, precision: str, budget_bytes: int, k_steps: int = 20, rounds: int = 2,
-               workgroups=(1024, 2048, 4096, 8192)):
-    """Fastest (tile shape, persistent workgroups) for a set of jets advanced
-    together.  jets: list of (params, inlet).  Returns (shape, workgroups, s)."""
-    import torch
+# search space of the batch tuner (coordinate descent, stage by stage)
+BATCH_WORKGROUPS = (0, 1024, 2048, 4096, 8192)  # 0: the device's resident count
+BATCH_COHORT_MIB = (64, 96, 112, 128, 160, 200, 0)  # 0: all jets in one cohort
+BATCH_STREAMS = (1, 2, 3)
+
+
+def batch_key(jets, precision: str) -> str:
+    """Cache key of a set of jets: precision, jet count and total population
+    bytes (to the nearest power of two) -- the two things the best cohort
+    split and grid depend on."""
+    import math
+    total = sum(lbm.bytes_required(p, precision) for p, _ in jets)
+    return (f"{_arch()}/{precision}/batch/{len(jets)}jets/"
+            f"{2 ** round(math.log2(max(total, 1 << 20)) - 20)}MiB")
+
+
+def apply_batch(b, cfg: dict) -> None:
+    """Put a tuned configuration (from tune_batch) on an lbm.Batch."""
+    b.set_launch(cfg["shape"], cfg["workgroups"])
+    b.set_cohort_bytes(cfg["cohort_mib"] << 20)
+    b.set_streams(cfg["streams"])
+
+
+def _time_batch(b, k_steps, rounds):
+    """Seconds per step of the batch's current configuration: one warm group
+    (captures its graphs), then the fastest of `rounds` timed groups."""
+    b.run(k_steps)
+    b.sync()
     best = None
-    with lbm.Batch(budget_bytes, len(jets), precision) as b:
+    for _ in range(rounds):
+        t0 = time.perf_counter()
+        b.run(k_steps)
+        b.sync()
+        dt = (time.perf_counter() - t0) / k_steps
+        best = dt if best is None else min(best, dt)
+    return best
+
+
+def tune_batch(jets, precision: str, retune: bool = False, k_steps: int = 50,
+               rounds: int = 3, shapes=None) -> dict:
+    """Fastest launch configuration for a set of jets advanced together in
+    one batch: tile shape, persistent workgroups, cohort size and number of
+    streams.  jets: list of (params, inlet).
+
+    Coordinate descent over the compiled tile shapes (with the batch's
+    default grid, cohorts and streams), then the grid, then cohort size and
+    stream count together, each stage keeping the best of the previous.  The
+    result is cached under batch_key (tuned once per GPU architecture,
+    precision and size class of the set) and returned as a dict for
+    apply_batch.  Every configuration gives the same bits; only the time
+    differs."""
+    key = batch_key(jets, precision)
+    db = _load()
+    infos = lbm.tile_shape_infos()
+    hit = db.get(key)
+    if hit is not None and not retune and hit.get("info") in infos:
+        cfg = dict(hit["config"])
+        cfg["shape"] = infos.index(hit["info"])
+        return cfg
+    budget = sum(lbm.bytes_required(p, precision) for p, _ in jets) + (64 << 20)
+    times = {}
+    with lbm.Batch(budget, len(jets), precision) as b:
         for p, inlet in jets:
             b.admit(p, inlet, 1 << 40)
-        for q in range(len(lbm.tile_shapes())):
-            for wg in workgroups:
-                b.set_launch(q, wg)
-                b.run(k_steps)
-                b.sync()
-                t0 = time.perf_counter()
-                for _ in range(rounds):
-                    b.run(k_steps)
-                b.sync()
-                dt = (time.perf_counter() - t0) / (rounds * k_steps)
-                if best is None or dt < best[2]:
-                    best = (q, wg, dt)
-    return best
+        cfg = {"shape": -1, "workgroups": 0, "cohort_mib": 128, "streams": 2}
+
+        def trial(**change):
+            c = dict(cfg, **change)
+            apply_batch(b, c)
+            t = _time_batch(b, k_steps, rounds)
+            times[json.dumps(c, sort_keys=True)] = t
+            return t, c
+
+        cand = range(len(infos)) if shapes is None else shapes
+        best = min((trial(shape=q) for q in cand), key=lambda tc: tc[0])
+        cfg = best[1]
+        best = min([best] + [trial(workgroups=w) for w in BATCH_WORKGROUPS
+                             if w != cfg["workgroups"]], key=lambda tc: tc[0])
+        cfg = best[1]
+        best = min([best] + [trial(cohort_mib=m, streams=n) for m in BATCH_COHORT_MIB
+                             for n in BATCH_STREAMS
+                             if (m, n) != (cfg["cohort_mib"], cfg["streams"])],
+                   key=lambda tc: tc[0])
+        cfg = best[1]
+    out = dict(cfg, s_per_step=best[0], trials=len(times))
+    db[key] = {"info": infos[cfg["shape"]], "config": {k: v for k, v in out.items()
+                                                       if k != "shape"},
+               "tuned_on": len(jets), "when": time.strftime("%Y-%m-%d %H:%M:%S")}
+    _save(db)
+    return out

@@ -210,3 +210,37 @@ def test_any_grid_size(layout, steps_per_launch):
         for q, (m, m0) in enumerate(zip(ms, base)):
             for key in m0:
                 assert np.array_equal(m[key], m0[key]), (grid, q, key)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+def test_tuned_batch_equals_default(tmp_path, monkeypatch, precision):
+    """The batch tuner searches tile shape, grid, cohort size and streams on a
+    set of jets, caches its pick under the set's key (a second call returns
+    it without timing), and the tuned batch gives bitwise the moments of the
+    batch with its default configuration."""
+    from paper_1002_3028_amd import autotune, lbm
+    monkeypatch.setenv("LBM_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    jets = _jets()
+    infos = lbm.tile_shape_infos()
+    # a quick search: the defaults' shapes plus one of each kind
+    one = [q for q, i in enumerate(infos) if i["steps"] == 1][:2]
+    two = [q for q, i in enumerate(infos) if i["steps"] == 2][-2:]
+    cfg = autotune.tune_batch([(p, inlet) for p, inlet, _ in jets], precision, k_steps=10,
+                              rounds=1, shapes=one + two)
+    assert cfg["shape"] in one + two and cfg["trials"] > 10
+    again = autotune.tune_batch([(p, inlet) for p, inlet, _ in jets], precision)
+    assert {k: again[k] for k in ("shape", "workgroups", "cohort_mib", "streams")} == \
+        {k: cfg[k] for k in ("shape", "workgroups", "cohort_mib", "streams")}
+    assert "trials" in again  # read from the cache, not retimed
+    out = []
+    for c in (cfg, None):
+        with lbm.Batch(1 << 30, 16, precision) as b:
+            if c is not None:
+                autotune.apply_batch(b, c)
+            slots = [b.admit(p, inlet, steps) for p, inlet, steps in jets]
+            for _ in range(10):
+                b.run(11)
+            out.append([b.moments(s) for s in slots])
+    for q in range(len(jets)):
+        for key in out[1][q]:
+            assert np.array_equal(out[0][q][key], out[1][q][key]), (q, key)
