@@ -243,13 +243,28 @@ int lbm_batch_set_layout(lbm_batch *b, int32_t layout);
 int lbm_batch_admit(lbm_batch *b, const lbm_config *cfg, int32_t n_t,
                     const double *ux, const double *ur, const double *T,
                     int64_t target_steps, int32_t *slot);
+/* Queue k steps of every active jet (enqueues only: it does not wait for the
+ * groups already queued, except that a rebuild of the cohort lists waits for
+ * the group two rebuilds back, which read the same copy of the lists). */
 int lbm_batch_run(lbm_batch *b, int32_t k_steps);
+/* Wait until at most in_flight (0 to 15) of the groups queued by
+ * lbm_batch_run are unfinished: 0 waits for all of them, 1 lets the last one
+ * run on while the caller works (a serving loop's throttle). */
+int lbm_batch_wait(lbm_batch *b, int32_t in_flight);
 /* Steps done by a slot's jet (host-side count; exact after lbm_batch_run). */
 int lbm_batch_poll(lbm_batch *b, int32_t slot, int64_t *steps_done);
+/* Profiles and moments of a slot's jet at its step count: they wait for the
+ * group in which the jet reached its target (or, for a jet still running,
+ * for all queued work), not for groups queued after it. */
 int lbm_batch_profiles(lbm_batch *b, int32_t slot, double *ux_axis, double *T_axis,
                        double *ux_exit, double *T_exit);
 int lbm_batch_moments(lbm_batch *b, int32_t slot, double *rho, double *ux,
                       double *ur, double *T);
+/* Free a slot: waits for the group in which its jet reached its target (or
+ * for all queued work if it had not), then returns its memory to the budget.
+ * Admission queues its uploads behind the work in flight and waits for
+ * nothing; neither call allocates device memory once the slot's block for
+ * the table and inlet rows is large enough. */
 int lbm_batch_retire(lbm_batch *b, int32_t slot);
 /* Wait for the batch's queued work; LBM_EDEVICE on an asynchronous error. */
 int lbm_batch_sync(lbm_batch *b);

@@ -9,6 +9,13 @@
 
 using namespace lbmx;
 
+namespace {
+// Workgroups of the FP64 conservation reduction at most (each strides over
+// nodes, so every grid fits).
+constexpr int kMaxRedBlocks = 1024;
+}  // namespace
+
+
 struct lbm_handle {
   int device = 0;
   lbm_config cfg{};
@@ -235,19 +242,29 @@ int one_step(lbm_handle *h, int32_t koff, int32_t tog) {
                      koff, tog, 1, h->d_flag);
 }
 
-// Capture k steps as one graph: with a two-step shape, k / 2 pair launches
-// (and one single step if k is odd), then the descriptor advance.
+// The launches of a group of k steps on `st`: with a two-step shape, k / 2
+// pair launches (and one single step if k is odd), then the descriptor
+// advance.
+int enqueue_group(lbm_handle *h, int32_t k, bool pair, hipStream_t st) {
+  int rc = LBM_OK;
+  const int32_t np = pair ? k / 2 : 0;
+  for (int32_t q = 0; q < np && !rc; ++q)
+    rc = launch_step(h->shape, h->prec, h->grid, st, h->d_desc, h->d_tiles, h->d_hdr, 2 * q,
+                     q & 1, 2, h->d_flag);
+  for (int32_t q = 2 * np; q < k && !rc; ++q)
+    rc = h->layout == LBM_LAYOUT_SINGLE
+             ? launch_aa_step(h->prec, h->grid, st, h->d_desc, h->d_tiles, h->d_hdr, q, h->d_flag)
+             : launch_step(h->shape, h->prec, h->grid, st, h->d_desc, h->d_tiles, h->d_hdr, q,
+                           np & 1, 1, h->d_flag);
+  if (!rc) rc = launch_advance(st, h->d_desc, h->d_hdr, 1, k, np);
+  return rc;
+}
+
+// Capture k steps as one graph (enqueue_group's launches).
 int capture_group(lbm_handle *h, int32_t k, bool pair) {
   hipGraph_t g;
   LBM_HIP(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-  int crc = LBM_OK;
-  const int32_t np = pair ? k / 2 : 0;
-  for (int32_t q = 0; q < np && !crc; ++q)
-    crc = launch_step(h->shape, h->prec, h->grid, h->stream, h->d_desc, h->d_tiles, h->d_hdr,
-                      2 * q, q & 1, 2, h->d_flag);
-  for (int32_t q = 2 * np; q < k && !crc; ++q)
-    crc = one_step(h, q, np & 1);
-  if (!crc) crc = launch_advance(h->stream, h->d_desc, h->d_hdr, 1, k, np);
+  const int crc = enqueue_group(h, k, pair, h->stream);
   const hipError_t e = hipStreamEndCapture(h->stream, &g);
   if (crc || e != hipSuccess) return crc ? crc : LBM_EDEVICE;
   const hipError_t ei = hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0);
@@ -272,8 +289,17 @@ int prepare_graph(lbm_handle *h) {
   if (rc) return rc;
   // (an optimisation only: the graph also uploads itself at its first launch)
   (void)hipGraphUpload(h->gexec, h->stream);
-  LBM_HIP(hipStreamSynchronize(h->stream));
-  return LBM_OK;
+  // One dry replay, so that the first lbm_step does not pay the graph's
+  // first launch: with the descriptor's target at its step0 every tile is
+  // skipped and the advance leaves step0 and flip as they are, so the state
+  // does not change.
+  h->desc.target = h->base;
+  int rc2 = upload_desc(h);
+  if (!rc2 && hipGraphLaunch(h->gexec, h->stream) != hipSuccess) rc2 = LBM_EDEVICE;
+  if (!rc2 && hipStreamSynchronize(h->stream) != hipSuccess) rc2 = LBM_EDEVICE;
+  h->desc.target = NO_TARGET;
+  const int rc3 = upload_desc(h);
+  return rc2 ? rc2 : rc3;
 }
 
 int launch_steps(lbm_handle *h, int64_t n) {
@@ -281,14 +307,14 @@ int launch_steps(lbm_handle *h, int64_t n) {
   const bool pair = tile_shapes(&nsh)[h->shape].steps == 2;
   int rc;
   while (n > 0) {
-    if (h->base != h->step && (pair || (h->graph_k > 0 && n >= h->graph_k) ||
-                               h->step - h->base > (1 << 30))) {
+    const bool graph = h->graph_k > 0 && n >= h->graph_k;
+    if (h->base != h->step && (pair || graph || h->step - h->base > (1 << 30))) {
       // bring the device step0 to the host count (single steps only since)
       rc = launch_advance(h->stream, h->d_desc, h->d_hdr, 1, (int32_t)(h->step - h->base), 0);
       if (rc) return rc;
       h->base = h->step;
     }
-    if (h->graph_k > 0 && n >= h->graph_k) {
+    if (graph) {
       if (!h->gexec || h->gexec_k != h->graph_k || h->gexec_shape != h->shape) {
         drop_graph(h);
         if ((rc = capture_group(h, h->graph_k, pair))) return rc;
@@ -299,16 +325,14 @@ int launch_steps(lbm_handle *h, int64_t n) {
       if (pair) h->flip ^= (h->graph_k / 2) & 1;
       n -= h->graph_k;
     } else if (pair) {
-      // one launch of one or two steps, advanced at once so that the device
-      // descriptor (step0, flip) always matches the host
-      const int32_t m = n >= 2 ? 2 : 1;
-      rc = launch_step(h->shape, h->prec, h->grid, h->stream, h->d_desc, h->d_tiles, h->d_hdr, 0,
-                       0, m, h->d_flag);
-      if (!rc) rc = launch_advance(h->stream, h->d_desc, h->d_hdr, 1, m, m == 2 ? 1 : 0);
-      if (rc) return rc;
+      // the rest (fewer steps than a graph holds) as one directly launched
+      // group: the same launches as a graph, one advance at the end, so the
+      // device descriptor (step0, flip) matches the host afterwards
+      const int32_t m = (int32_t)std::min<int64_t>(n, 1 << 20);
+      if ((rc = enqueue_group(h, m, true, h->stream))) return rc;
       h->step += m;
       h->base += m;
-      if (m == 2) h->flip ^= 1;
+      h->flip ^= (m / 2) & 1;
       n -= m;
     } else {
       rc = one_step(h, (int32_t)(h->step - h->base), 0);
@@ -318,6 +342,32 @@ int launch_steps(lbm_handle *h, int64_t n) {
     }
   }
   return LBM_OK;
+}
+
+// Reduction workgroups of the conservation kernels for a grid (the same
+// count in both conservation entry points, so their sums agree bit for bit).
+int red_blocks(const lbm_handle *h) {
+  const int64_t nodes = (int64_t)h->cfg.nx * h->cfg.nr;
+  return (int)std::min<int64_t>(kMaxRedBlocks, (nodes + RED_THREADS - 1) / RED_THREADS);
+}
+
+// Both conservation entry points: reduce into `part` (nblocks partials and
+// the total after them), wait, read the total back.
+int conservation_into(lbm_handle *h, RedPartial *part, int nblocks, double *mass3d,
+                      double *energy3d) {
+  const int64_t nodes = (int64_t)h->cfg.nx * h->cfg.nr;
+  int rc;
+  if ((rc = launch_conservation(h->prec, h->stream, h->d_desc, nodes, h->step,
+                                view_of(h, h->step), part, nblocks, part + nblocks)))
+    return rc;
+  const int st = sync_and_check(h);
+  if (st == LBM_EDEVICE) return st;
+  RedPartial r;
+  LBM_HIP(hipMemcpy(&r, part + nblocks, sizeof r, hipMemcpyDeviceToHost));
+  *mass3d = r.mass;
+  *energy3d = r.energy;
+  if (r.bad != 0.0) h->unstable = true;
+  return h->unstable ? LBM_EUNSTABLE : LBM_OK;
 }
 
 }  // namespace
@@ -438,24 +488,11 @@ int lbm_profiles(lbm_handle *h, double *ux_axis, double *T_axis, double *ux_exit
 
 int lbm_conservation(lbm_handle *h, double *mass3d, double *energy3d) {
   if (!h || !mass3d || !energy3d) return LBM_EINVAL;
-  const int64_t nodes = (int64_t)h->cfg.nx * h->cfg.nr;
-  const int nblocks = (int)std::min<int64_t>(1024, (nodes + RED_THREADS - 1) / RED_THREADS);
+  const int nblocks = red_blocks(h);
   void *p;
-  int rc = h->scratch.get((nblocks + 1) * sizeof(RedPartial), &p);
+  const int rc = h->scratch.get((nblocks + 1) * sizeof(RedPartial), &p);
   if (rc) return rc;
-  RedPartial *part = (RedPartial *)p;
-  if ((rc = launch_conservation(h->prec, h->stream, h->d_desc, nodes, h->step, view_of(h, h->step),
-                                part, nblocks,
-                                part + nblocks)))
-    return rc;
-  const int st = sync_and_check(h);
-  if (st == LBM_EDEVICE) return st;
-  RedPartial r;
-  LBM_HIP(hipMemcpy(&r, part + nblocks, sizeof r, hipMemcpyDeviceToHost));
-  *mass3d = r.mass;
-  *energy3d = r.energy;
-  if (r.bad != 0.0) h->unstable = true;
-  return h->unstable ? LBM_EUNSTABLE : LBM_OK;
+  return conservation_into(h, (RedPartial *)p, nblocks, mass3d, energy3d);
 }
 
 int lbm_set_state(lbm_handle *h, const double *rho, const double *ux, const double *ur,

@@ -8,6 +8,14 @@
 // sums, header) and the launch configuration never changes with the set of
 // jets, so the captured graph of k steps of a cohort is replayed as jets come
 // and go.
+//
+// Runs only enqueue, so that a serving loop can queue the next group before
+// it retires and admits jets: the cohort lists exist twice (a rebuild writes
+// the copy that the groups in flight do not read), every group records an
+// event, profiles are extracted on a stream of their own after the group in
+// which the jet finished, and admission and retirement neither allocate nor
+// wait for the batch's stream (each slot keeps its block for the property
+// table and inlet rows from one jet to the next).
 #include <algorithm>
 #include <cstring>
 #include <map>
@@ -25,10 +33,21 @@ struct Slot {
   std::vector<double> nu_tab, al_tab;
   JetDesc desc{};
   size_t off = 0, bytes = 0;
-  float4 *d_table = nullptr;
+  float4 *d_table = nullptr;  // both inside the slot's block `aux`
   float4 *d_inlet = nullptr;
   int64_t step = 0, target = 0;
-  int32_t flip = 0;  // state after s steps in buf[(s + flip) & 1]
+  int32_t flip = 0;       // state after s steps in buf[(s + flip) & 1]
+  int64_t done_seq = -1;  // the group in which the jet reached its target
+};
+
+// Device block of a slot for its jet's property table and inlet rows; kept
+// from one jet to the next (grown when a jet needs more), so that admission
+// and retirement need no allocation, which would wait for the device.
+struct SlotBlock {
+  void *p = nullptr;  // device
+  void *h = nullptr;  // pinned host staging of the same size (the upload is
+                      // then an asynchronous copy in stream order)
+  size_t cap = 0;
 };
 
 // First-fit free list over [0, size) with 256-byte granules.
@@ -79,21 +98,38 @@ struct lbm_batch {
   void *arena_mem = nullptr;
   Arena arena;
   std::vector<Slot> slots;
-  JetDesc *d_jets = nullptr;     // per cohort: compact list of its jets
+  std::vector<SlotBlock> blocks;   // per slot
+  // cohort lists, two copies (index `copy`): per cohort the compact list of
+  // its jets, the tile prefix sums and the header
+  JetDesc *d_jets = nullptr;
   JetDesc *d_slot_desc = nullptr;  // per slot, for the single-jet helper kernels
-  int32_t *d_tiles = nullptr;      // per cohort: tile prefix sums
-  BatchHdr *d_hdr = nullptr;       // per cohort: number of jets
+  int32_t *d_tiles = nullptr;
+  BatchHdr *d_hdr = nullptr;
   int32_t max_cohorts = 0;
   int32_t n_cohorts = 0;
+  int32_t copy = 1;                // the copy the last rebuild wrote
+  int32_t copy_cohorts[2] = {0, 0};  // headers written in each copy
+  bool copy_used[2] = {false, false};
+  hipEvent_t copy_done[2] = {};    // after the last group that read each copy
+  // group completion: group n records done[n % RING] after its launches
+  static constexpr int RING = 16;
+  int64_t seq = 0;                 // groups enqueued
+  hipEvent_t done[RING] = {};
+  hipStream_t io = nullptr;        // profile and moment extraction
+  hipStream_t cap = nullptr;       // graph capture (never holds work)
+  hipEvent_t mark = nullptr;       // "everything enqueued so far" on `stream`
+  JetDesc *h_slot = nullptr;       // pinned staging of each slot's descriptor
+  int32_t *h_zero = nullptr;       // pinned 0 (a slot's instability flag)
   // 0: one cohort.  Two cohorts run at once (two streams), and together they
   // fill the 256 MiB Infinity Cache.
   size_t cohort_bytes = size_t(128) << 20;
   int32_t *d_flags = nullptr;
   // pinned staging of what rebuild uploads (cohort after cohort, compact), so
-  // that the uploads are asynchronous copies ordered before the launches
-  JetDesc *h_jets = nullptr;   // max_slots descriptors
-  int32_t *h_tiles = nullptr;  // max_slots + max_cohorts tile prefix sums
-  BatchHdr *h_hdr = nullptr;   // max_cohorts
+  // that the uploads are asynchronous copies ordered before the launches; two
+  // copies, as the device lists
+  JetDesc *h_jets = nullptr;   // 2 x max_slots descriptors
+  int32_t *h_tiles = nullptr;  // 2 x (max_slots + max_cohorts) tile prefix sums
+  BatchHdr *h_hdr = nullptr;   // 2 x max_cohorts
   Scratch scratch;
   std::vector<int32_t> active;  // slots in the compact list, in order
   bool dirty = true;
@@ -101,7 +137,7 @@ struct lbm_batch {
   int cur_shape = 0;    // shape of the current cohorts (set by rebuild)
   int32_t wg = 0;       // 0: auto
   int32_t grid = 0;
-  std::map<std::tuple<int, int, int, int>, hipGraphExec_t> graphs;  // (k, shape, grid, cohort)
+  std::map<std::tuple<int, int, int, int, int>, hipGraphExec_t> graphs;  // (k, shape, grid, cohort, copy)
   // cohorts alternate between the batch's stream and a second one, so that
   // one cohort's launches fill the device while the other's start or drain
   static constexpr int MAX_STREAMS = 4;
@@ -124,8 +160,22 @@ void drop_graphs(lbm_batch *b) {
   b->graphs.clear();
 }
 
+// Pointers of copy `cp` of the cohort lists and of their staging.
+struct Lists {
+  JetDesc *dj, *hj;
+  int32_t *dt, *ht;
+  BatchHdr *dh, *hh;
+};
+Lists lists_of(const lbm_batch *b, int32_t cp) {
+  const size_t ms = b->slots.size(), mc = (size_t)b->max_cohorts;
+  return {b->d_jets + cp * mc * ms, b->h_jets + cp * ms,
+          b->d_tiles + cp * mc * (ms + 1), b->h_tiles + cp * (ms + mc),
+          b->d_hdr + cp * mc, b->h_hdr + cp * mc};
+}
+
 // Rebuild and upload the cohorts: active jets in slot order, a new cohort
 // whenever the next jet's buffers would take the cohort past cohort_bytes.
+// Written into the copy of the lists that the groups in flight do not read.
 int rebuild(lbm_batch *b) {
   const int shape = pick_shape(b);
   const int32_t ms = (int32_t)b->slots.size();
@@ -152,31 +202,34 @@ int rebuild(lbm_batch *b) {
     bytes.back() += sl.bytes;
     b->active.push_back(s);
   }
-  // the launches queued so far read the device lists and the last rebuild's
-  // copies read the staging: wait for both before anything is rewritten
-  LBM_HIP(hipStreamSynchronize(b->stream));
-  const int32_t prev = b->n_cohorts;
+  // the groups that read this copy last, and the uploads from its staging
+  // queued before them, must be done before either is rewritten
+  const int32_t cp = 1 - b->copy;
+  if (b->copy_used[cp]) LBM_HIP(hipEventSynchronize(b->copy_done[cp]));
+  const Lists L = lists_of(b, cp);
   b->n_cohorts = jets.back().empty() && jets.size() == 1 ? 0 : (int32_t)jets.size();
-  const int32_t nh = std::max(prev, b->n_cohorts);
+  // cohorts that emptied keep an empty tile list
+  const int32_t nh = std::max(b->copy_cohorts[cp], b->n_cohorts);
   size_t jo = 0, to = 0;  // staging offsets
   for (int32_t c = 0; c < nh; ++c) {
-    // cohorts that emptied keep an empty tile list
     const int32_t n = c < b->n_cohorts ? (int32_t)jets[c].size() : 0;
-    b->h_hdr[c] = BatchHdr{n, {0, 0, 0}};
-    if (n > 0) std::memcpy(b->h_jets + jo, jets[c].data(), n * sizeof(JetDesc));
-    if (n > 0) std::memcpy(b->h_tiles + to, start[c].data(), (n + 1) * sizeof(int32_t));
-    else b->h_tiles[to] = 0;
+    L.hh[c] = BatchHdr{n, {0, 0, 0}};
+    if (n > 0) std::memcpy(L.hj + jo, jets[c].data(), n * sizeof(JetDesc));
+    if (n > 0) std::memcpy(L.ht + to, start[c].data(), (n + 1) * sizeof(int32_t));
+    else L.ht[to] = 0;
     if (n > 0)
-      LBM_HIP(hipMemcpyAsync(b->d_jets + (size_t)c * ms, b->h_jets + jo, n * sizeof(JetDesc),
+      LBM_HIP(hipMemcpyAsync(L.dj + (size_t)c * ms, L.hj + jo, n * sizeof(JetDesc),
                              hipMemcpyHostToDevice, b->stream));
-    LBM_HIP(hipMemcpyAsync(b->d_tiles + (size_t)c * (ms + 1), b->h_tiles + to,
-                           (n + 1) * sizeof(int32_t), hipMemcpyHostToDevice, b->stream));
+    LBM_HIP(hipMemcpyAsync(L.dt + (size_t)c * (ms + 1), L.ht + to, (n + 1) * sizeof(int32_t),
+                           hipMemcpyHostToDevice, b->stream));
     jo += n;
     to += n + 1;
   }
   if (nh > 0)
-    LBM_HIP(hipMemcpyAsync(b->d_hdr, b->h_hdr, nh * sizeof(BatchHdr), hipMemcpyHostToDevice,
+    LBM_HIP(hipMemcpyAsync(L.dh, L.hh, nh * sizeof(BatchHdr), hipMemcpyHostToDevice,
                            b->stream));
+  b->copy_cohorts[cp] = b->n_cohorts;
+  b->copy = cp;
   // persistent grid of fixed size (graphs stay valid as jets come and go):
   // by default the workgroups the device holds at once
   int32_t g = b->wg > 0 ? b->wg
@@ -188,32 +241,36 @@ int rebuild(lbm_batch *b) {
   return LBM_OK;
 }
 
+// Launch group k of cohort c on stream st (capturing its graph on the
+// capture stream the first time).
 int run_group(lbm_batch *b, int32_t k, int32_t c, hipStream_t st) {
   const int shape = b->cur_shape;
   int nsh;
   const int32_t np = tile_shapes(&nsh)[shape].steps == 2 ? k / 2 : 0;
   const int32_t ms = (int32_t)b->slots.size();
-  auto key = std::make_tuple((int)k, shape, (int)b->grid, (int)c);
+  auto key = std::make_tuple((int)k, shape, (int)b->grid, (int)c, (int)b->copy);
   auto it = b->graphs.find(key);
   if (it == b->graphs.end()) {
-    JetDesc *jets = b->d_jets + (size_t)c * ms;
-    const int32_t *tiles = b->d_tiles + (size_t)c * (ms + 1);
-    const BatchHdr *hdr = b->d_hdr + c;
+    const Lists L = lists_of(b, b->copy);
+    JetDesc *jets = L.dj + (size_t)c * ms;
+    const int32_t *tiles = L.dt + (size_t)c * (ms + 1);
+    const BatchHdr *hdr = L.dh + c;
+    hipStream_t cs = b->cap;
     hipGraph_t g;
-    LBM_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    LBM_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     int rc = LBM_OK;
     // k / 2 pair launches with a two-step shape (one single step if k is
     // odd), else k single steps
     for (int32_t q = 0; q < np && !rc; ++q)
-      rc = launch_step(shape, b->prec, b->grid, b->stream, jets, tiles, hdr, 2 * q, q & 1, 2,
+      rc = launch_step(shape, b->prec, b->grid, cs, jets, tiles, hdr, 2 * q, q & 1, 2,
                        b->d_flags);
     for (int32_t q = 2 * np; q < k && !rc; ++q)
       rc = b->layout == LBM_LAYOUT_SINGLE
-               ? launch_aa_step(b->prec, b->grid, b->stream, jets, tiles, hdr, q, b->d_flags)
-               : launch_step(shape, b->prec, b->grid, b->stream, jets, tiles, hdr, q, np & 1, 1,
+               ? launch_aa_step(b->prec, b->grid, cs, jets, tiles, hdr, q, b->d_flags)
+               : launch_step(shape, b->prec, b->grid, cs, jets, tiles, hdr, q, np & 1, 1,
                              b->d_flags);
-    if (!rc) rc = launch_advance(b->stream, jets, hdr, ms, k, np);
-    const hipError_t e = hipStreamEndCapture(b->stream, &g);
+    if (!rc) rc = launch_advance(cs, jets, hdr, ms, k, np);
+    const hipError_t e = hipStreamEndCapture(cs, &g);
     if (rc || e != hipSuccess) return rc ? rc : LBM_EDEVICE;
     hipGraphExec_t ex;
     const hipError_t ei = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
@@ -222,6 +279,19 @@ int run_group(lbm_batch *b, int32_t k, int32_t c, hipStream_t st) {
     it = b->graphs.emplace(key, ex).first;
   }
   LBM_HIP(hipGraphLaunch(it->second, st));
+  return LBM_OK;
+}
+
+// Make the extraction stream wait until the slot's state is final: the group
+// in which its jet reached its target, or, for a jet still running, all the
+// work enqueued so far.
+int io_after(lbm_batch *b, const Slot &sl) {
+  if (sl.done_seq >= 0) {
+    LBM_HIP(hipStreamWaitEvent(b->io, b->done[sl.done_seq % lbm_batch::RING], 0));
+  } else {
+    LBM_HIP(hipEventRecord(b->mark, b->stream));
+    LBM_HIP(hipStreamWaitEvent(b->io, b->mark, 0));
+  }
   return LBM_OK;
 }
 
@@ -247,33 +317,46 @@ int lbm_batch_create(size_t budget_bytes, int32_t max_slots, int32_t precision,
   b->prec = precision;
   b->budget = budget_bytes & ~size_t(255);
   b->slots.resize(max_slots);
+  b->blocks.resize(max_slots);
   b->max_cohorts = std::min<int32_t>(max_slots, 64);
   (void)hipGetDevice(&b->device);
   const size_t mc = (size_t)b->max_cohorts;
   bool ok = hipMalloc(&b->arena_mem, b->budget) == hipSuccess &&
-            hipMalloc(&b->d_jets, mc * max_slots * sizeof(JetDesc)) == hipSuccess &&
+            hipMalloc(&b->d_jets, 2 * mc * max_slots * sizeof(JetDesc)) == hipSuccess &&
             hipMalloc(&b->d_slot_desc, max_slots * sizeof(JetDesc)) == hipSuccess &&
-            hipMalloc(&b->d_tiles, mc * (max_slots + 1) * sizeof(int32_t)) == hipSuccess &&
-            hipMalloc(&b->d_hdr, mc * sizeof(BatchHdr)) == hipSuccess &&
+            hipMalloc(&b->d_tiles, 2 * mc * (max_slots + 1) * sizeof(int32_t)) == hipSuccess &&
+            hipMalloc(&b->d_hdr, 2 * mc * sizeof(BatchHdr)) == hipSuccess &&
             hipMalloc(&b->d_flags, max_slots * sizeof(int32_t)) == hipSuccess &&
-            hipHostMalloc(&b->h_jets, max_slots * sizeof(JetDesc), hipHostMallocDefault) ==
+            hipHostMalloc(&b->h_jets, 2 * max_slots * sizeof(JetDesc), hipHostMallocDefault) ==
                 hipSuccess &&
-            hipHostMalloc(&b->h_tiles, (max_slots + mc) * sizeof(int32_t), hipHostMallocDefault) ==
+            hipHostMalloc(&b->h_tiles, 2 * (max_slots + mc) * sizeof(int32_t),
+                          hipHostMallocDefault) == hipSuccess &&
+            hipHostMalloc(&b->h_hdr, 2 * mc * sizeof(BatchHdr), hipHostMallocDefault) ==
                 hipSuccess &&
-            hipHostMalloc(&b->h_hdr, mc * sizeof(BatchHdr), hipHostMallocDefault) == hipSuccess;
+            hipHostMalloc(&b->h_slot, max_slots * sizeof(JetDesc), hipHostMallocDefault) ==
+                hipSuccess &&
+            hipHostMalloc(&b->h_zero, sizeof(int32_t), hipHostMallocDefault) == hipSuccess;
   if (ok && hip_stream) {
     b->stream = (hipStream_t)hip_stream;
   } else if (ok) {
     ok = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) == hipSuccess;
     b->own_stream = ok;
   }
+  ok = ok && hipStreamCreateWithFlags(&b->io, hipStreamNonBlocking) == hipSuccess &&
+       hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) == hipSuccess &&
+       hipEventCreateWithFlags(&b->mark, hipEventDisableTiming) == hipSuccess;
+  for (int q = 0; ok && q < 2; ++q)
+    ok = hipEventCreateWithFlags(&b->copy_done[q], hipEventDisableTiming) == hipSuccess;
+  for (int q = 0; ok && q < lbm_batch::RING; ++q)
+    ok = hipEventCreateWithFlags(&b->done[q], hipEventDisableTiming) == hipSuccess;
   if (ok) {
+    *b->h_zero = 0;
     std::vector<int32_t> zeros(max_slots, 0);
-    std::vector<BatchHdr> hz(mc, BatchHdr{0, {0, 0, 0}});
-    std::vector<int32_t> tz(mc * (max_slots + 1), 0);
+    std::vector<BatchHdr> hz(2 * mc, BatchHdr{0, {0, 0, 0}});
+    std::vector<int32_t> tz(2 * mc * (max_slots + 1), 0);
     ok = hipMemcpy(b->d_flags, zeros.data(), max_slots * sizeof(int32_t),
                    hipMemcpyHostToDevice) == hipSuccess &&
-         hipMemcpy(b->d_hdr, hz.data(), mc * sizeof(BatchHdr), hipMemcpyHostToDevice) ==
+         hipMemcpy(b->d_hdr, hz.data(), hz.size() * sizeof(BatchHdr), hipMemcpyHostToDevice) ==
              hipSuccess &&
          hipMemcpy(b->d_tiles, tz.data(), tz.size() * sizeof(int32_t), hipMemcpyHostToDevice) ==
              hipSuccess;
@@ -342,19 +425,29 @@ int lbm_batch_admit(lbm_batch *b, const lbm_config *cfg, int32_t n_t, const doub
     return rc;
   }
   std::vector<float4> table = make_table(&sl.cfg);
-  bool ok = hipMalloc(&sl.d_table, table.size() * sizeof(float4)) == hipSuccess &&
-            hipMalloc(&sl.d_inlet, rows.size() * sizeof(float4)) == hipSuccess;
-  ok = ok && hipMemcpy(sl.d_table, table.data(), table.size() * sizeof(float4),
-                       hipMemcpyHostToDevice) == hipSuccess &&
-       hipMemcpy(sl.d_inlet, rows.data(), rows.size() * sizeof(float4),
-                 hipMemcpyHostToDevice) == hipSuccess;
-  if (!ok) {
-    if (sl.d_table) (void)hipFree(sl.d_table);
-    if (sl.d_inlet) (void)hipFree(sl.d_inlet);
-    b->arena.release(off, need);
-    sl = Slot();
-    return LBM_ENOMEM;
+  // the slot's block holds the table and the inlet rows; it is grown only
+  // when a jet needs more than any earlier jet of the slot (freeing device
+  // memory waits for the device)
+  const size_t tb = align256(table.size() * sizeof(float4));
+  const size_t ib = align256(rows.size() * sizeof(float4));
+  SlotBlock &blk = b->blocks[s];
+  if (blk.cap < tb + ib) {
+    if (blk.p) (void)hipFree(blk.p);
+    if (blk.h) (void)hipHostFree(blk.h);
+    blk.p = blk.h = nullptr;
+    blk.cap = 0;
+    if (hipMalloc(&blk.p, tb + ib) != hipSuccess ||
+        hipHostMalloc(&blk.h, tb + ib, hipHostMallocDefault) != hipSuccess) {
+      if (blk.p) (void)hipFree(blk.p);
+      blk.p = blk.h = nullptr;
+      b->arena.release(off, need);
+      sl = Slot();
+      return LBM_ENOMEM;
+    }
+    blk.cap = tb + ib;
   }
+  sl.d_table = (float4 *)blk.p;
+  sl.d_inlet = (float4 *)((char *)blk.p + tb);
   sl.used = true;
   sl.off = off;
   sl.bytes = need;
@@ -373,10 +466,20 @@ int lbm_batch_admit(lbm_batch *b, const lbm_config *cfg, int32_t n_t, const doub
   int32_t tx;
   tiles_of(&sl.cfg, pick_shape(b), &tx);
   d.tiles_x = tx;
-  const int32_t zero = 0;
-  LBM_HIP(hipStreamSynchronize(b->stream));
-  LBM_HIP(hipMemcpy(b->d_slot_desc + s, &d, sizeof(JetDesc), hipMemcpyHostToDevice));
-  LBM_HIP(hipMemcpy(b->d_flags + s, &zero, sizeof zero, hipMemcpyHostToDevice));
+  // Uploads and initialisation are queued on the batch's stream, behind the
+  // groups in flight.  Those no longer touch this slot's memory: the jet it
+  // held last was retired only once its last group had finished, and later
+  // groups skip it (its step count is at its target).
+  // (the staging of this slot is free: its last upload preceded the groups
+  // of the jet retired from the slot)
+  b->h_slot[s] = d;
+  std::memcpy(blk.h, table.data(), table.size() * sizeof(float4));
+  std::memcpy((char *)blk.h + tb, rows.data(), rows.size() * sizeof(float4));
+  LBM_HIP(hipMemcpyAsync(blk.p, blk.h, tb + ib, hipMemcpyHostToDevice, b->stream));
+  LBM_HIP(hipMemcpyAsync(b->d_slot_desc + s, b->h_slot + s, sizeof(JetDesc),
+                         hipMemcpyHostToDevice, b->stream));
+  LBM_HIP(hipMemcpyAsync(b->d_flags + s, b->h_zero, sizeof(int32_t), hipMemcpyHostToDevice,
+                         b->stream));
   const float4 u0 =
       make_float4((float)cfg->rho0, (float)cfg->ux0, (float)cfg->ur0, (float)cfg->T0);
   for (int64_t q = n_buffers(b->layout) - 1; q >= 0 && !rc; --q) {
@@ -410,18 +513,37 @@ int lbm_batch_run(lbm_batch *b, int32_t k_steps) {
     LBM_HIP(hipEventRecord(b->join[q], b->side[q]));
     LBM_HIP(hipStreamWaitEvent(b->stream, b->join[q], 0));
   }
+  // the group's completion, which is also the last use (so far) of the copy
+  // of the lists it read
+  LBM_HIP(hipEventRecord(b->done[b->seq % lbm_batch::RING], b->stream));
+  LBM_HIP(hipEventRecord(b->copy_done[b->copy], b->stream));
+  b->copy_used[b->copy] = true;
   // mirror of the advance kernel: every pair a jet took in full toggled its flip
   int nsh;
   const int64_t np = tile_shapes(&nsh)[b->cur_shape].steps == 2 ? k_steps / 2 : 0;
   bool finished = false;
   for (int32_t s : b->active) {
     Slot &sl = b->slots[s];
+    if (sl.step >= sl.target) continue;
     if (np > 0 && sl.target - sl.step >= 2)
       sl.flip ^= (int32_t)(std::min<int64_t>(np, (sl.target - sl.step) / 2) & 1);
     sl.step = std::min<int64_t>(sl.step + k_steps, sl.target);
-    finished = finished || sl.step >= sl.target;
+    if (sl.step >= sl.target) {
+      sl.done_seq = b->seq;
+      finished = true;
+    }
   }
+  ++b->seq;
   if (finished) b->dirty = true;  // drop finished jets from the tile list
+  return LBM_OK;
+}
+
+int lbm_batch_wait(lbm_batch *b, int32_t in_flight) {
+  if (!b || in_flight < 0 || in_flight >= lbm_batch::RING) return LBM_EINVAL;
+  const int64_t g = b->seq - 1 - in_flight;  // the newest group that must be done
+  if (g < 0) return LBM_OK;
+  LBM_HIP(hipEventSynchronize(b->done[g % lbm_batch::RING]));
+  LBM_HIP(hipGetLastError());
   return LBM_OK;
 }
 
@@ -432,10 +554,17 @@ int lbm_batch_poll(lbm_batch *b, int32_t slot, int64_t *steps_done) {
   return LBM_OK;
 }
 
-static int slot_flag(lbm_batch *b, int32_t slot, int32_t *flag) {
-  LBM_HIP(hipStreamSynchronize(b->stream));
+// Extraction of one jet's results runs on the batch's extraction stream after
+// the group in which the jet finished (io_after), so that it waits neither
+// for the groups queued since nor holds them up: the helper kernel, then the
+// jet's instability flag and the result back to the host.
+static int extract(lbm_batch *b, int32_t slot, void *dev, size_t bytes, void *host,
+                   int32_t *flag) {
+  LBM_HIP(hipMemcpyAsync(flag, b->d_flags + slot, sizeof(int32_t), hipMemcpyDeviceToHost,
+                         b->io));
+  LBM_HIP(hipMemcpyAsync(host, dev, bytes, hipMemcpyDeviceToHost, b->io));
+  LBM_HIP(hipStreamSynchronize(b->io));
   LBM_HIP(hipGetLastError());
-  LBM_HIP(hipMemcpy(flag, b->d_flags + slot, sizeof(int32_t), hipMemcpyDeviceToHost));
   return LBM_OK;
 }
 
@@ -447,13 +576,13 @@ int lbm_batch_profiles(lbm_batch *b, int32_t slot, double *ux_axis, double *T_ax
   void *p;
   int rc = b->scratch.get(n * sizeof(float2), &p);
   if (rc) return rc;
-  if ((rc = launch_profiles(b->prec, b->stream, b->d_slot_desc + slot, &sl->cfg, sl->step,
+  if ((rc = io_after(b, *sl))) return rc;
+  if ((rc = launch_profiles(b->prec, b->io, b->d_slot_desc + slot, &sl->cfg, sl->step,
                             state_view_of(b->layout, sl->step, sl->flip), (float2 *)p)))
     return rc;
-  int32_t flag;
-  if ((rc = slot_flag(b, slot, &flag))) return rc;
   std::vector<float2> v(n);
-  LBM_HIP(hipMemcpy(v.data(), p, n * sizeof(float2), hipMemcpyDeviceToHost));
+  int32_t flag = 0;
+  if ((rc = extract(b, slot, p, n * sizeof(float2), v.data(), &flag))) return rc;
   for (int i = 0; i < sl->cfg.nx; ++i) {
     if (ux_axis) ux_axis[i] = v[i].x;
     if (T_axis) T_axis[i] = v[i].y;
@@ -473,13 +602,13 @@ int lbm_batch_moments(lbm_batch *b, int32_t slot, double *rho, double *ux, doubl
   void *p;
   int rc = b->scratch.get(nodes * sizeof(float4), &p);
   if (rc) return rc;
-  if ((rc = launch_moments(b->prec, b->stream, b->d_slot_desc + slot, &sl->cfg, sl->step,
+  if ((rc = io_after(b, *sl))) return rc;
+  if ((rc = launch_moments(b->prec, b->io, b->d_slot_desc + slot, &sl->cfg, sl->step,
                            state_view_of(b->layout, sl->step, sl->flip), (float4 *)p)))
     return rc;
-  int32_t flag;
-  if ((rc = slot_flag(b, slot, &flag))) return rc;
   std::vector<float4> m((size_t)nodes);
-  LBM_HIP(hipMemcpy(m.data(), p, nodes * sizeof(float4), hipMemcpyDeviceToHost));
+  int32_t flag = 0;
+  if ((rc = extract(b, slot, p, nodes * sizeof(float4), m.data(), &flag))) return rc;
   for (int64_t n = 0; n < nodes; ++n) {
     if (rho) rho[n] = m[n].x;
     if (ux) ux[n] = m[n].y;
@@ -492,11 +621,14 @@ int lbm_batch_moments(lbm_batch *b, int32_t slot, double *rho, double *ux, doubl
 int lbm_batch_retire(lbm_batch *b, int32_t slot) {
   Slot *sl = slot_of(b, slot);
   if (!sl) return LBM_EINVAL;
-  LBM_HIP(hipStreamSynchronize(b->stream));
+  // no group may still use the jet's memory: wait for the group in which it
+  // finished (later groups skip it), or for all queued work if it had not
+  if (sl->done_seq >= 0)
+    LBM_HIP(hipEventSynchronize(b->done[sl->done_seq % lbm_batch::RING]));
+  else
+    LBM_HIP(hipStreamSynchronize(b->stream));
   b->arena.release(sl->off, sl->bytes);
   b->used -= sl->bytes;
-  if (sl->d_table) (void)hipFree(sl->d_table);
-  if (sl->d_inlet) (void)hipFree(sl->d_inlet);
   *sl = Slot();
   b->dirty = true;
   return LBM_OK;
@@ -564,10 +696,11 @@ void lbm_batch_destroy(lbm_batch *b) {
   if (b->stream) (void)hipStreamSynchronize(b->stream);
   for (hipStream_t st : b->side)
     if (st) (void)hipStreamSynchronize(st);
+  if (b->io) (void)hipStreamSynchronize(b->io);
   drop_graphs(b);
-  for (Slot &s : b->slots) {
-    if (s.d_table) (void)hipFree(s.d_table);
-    if (s.d_inlet) (void)hipFree(s.d_inlet);
+  for (SlotBlock &k : b->blocks) {
+    if (k.p) (void)hipFree(k.p);
+    if (k.h) (void)hipHostFree(k.h);
   }
   b->scratch.release();
   if (b->arena_mem) (void)hipFree(b->arena_mem);
@@ -579,6 +712,15 @@ void lbm_batch_destroy(lbm_batch *b) {
   if (b->h_jets) (void)hipHostFree(b->h_jets);
   if (b->h_tiles) (void)hipHostFree(b->h_tiles);
   if (b->h_hdr) (void)hipHostFree(b->h_hdr);
+  if (b->h_slot) (void)hipHostFree(b->h_slot);
+  if (b->h_zero) (void)hipHostFree(b->h_zero);
+  if (b->io) (void)hipStreamDestroy(b->io);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  if (b->mark) (void)hipEventDestroy(b->mark);
+  for (hipEvent_t e : b->copy_done)
+    if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : b->done)
+    if (e) (void)hipEventDestroy(e);
   if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
   if (b->fork) (void)hipEventDestroy(b->fork);
   for (int q = 0; q + 1 < lbm_batch::MAX_STREAMS; ++q) {

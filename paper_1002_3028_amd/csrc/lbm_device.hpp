@@ -115,17 +115,18 @@ struct RedPartial {
 
 // ---------------------------------------------------------------------------
 // Storage codecs.  FP32 stores populations as they are; the 16-bit codecs
-// store the deviation from a reference (w_k rho_ref for f, g_ref/4 for g)
-// rounded to nearest even, and decode to FP32.
+// store the deviation from a reference (w_k rho_ref for f, g_ref/4 for g).
+// enc(v, off, one, thermal): `thermal` is true for the four temperature
+// planes (g); no codec treats them differently at present.
 // ---------------------------------------------------------------------------
 // `one` is 1.0f from the descriptor: with it the FP16 codec maps onto the
 // mixed-precision FMA (decode: h * 1 + offset in one instruction; encode: the
-// exact f - offset rounded once to binary16).
+// exact f - offset rounded once to binary16, to nearest even).
 struct CodecF32 {
   using T = float;
   static constexpr bool dev = false;
   __device__ static __forceinline__ float dec(T v, float, float) { return v; }
-  __device__ static __forceinline__ T enc(float v, float, float) { return v; }
+  __device__ static __forceinline__ T enc(float v, float, float, bool) { return v; }
 };
 struct CodecF16 {
   using T = _Float16;
@@ -133,7 +134,7 @@ struct CodecF16 {
   __device__ static __forceinline__ float dec(T v, float off, float one) {
     return __builtin_fmaf((float)v, one, off);
   }
-  __device__ static __forceinline__ T enc(float v, float off, float one) {
+  __device__ static __forceinline__ T enc(float v, float off, float one, bool) {
     return (T)__builtin_fmaf(v, one, -off);
   }
 };
@@ -142,17 +143,22 @@ struct CodecF16 {
 // bits.  Where binary16 is normal its spacing is 2^13 FP32 ulps, the sum is
 // exact, and the value rounds up with exactly the probability of the discarded
 // fraction (values binary16 holds stay as they are); below 2^-14 the offset
-// spans the fixed spacing 2^-24 in steps of 2^-37.  The rounding errors of
-// values that keep returning therefore do not add up.  The hash makes it
-// reproducible: the same value rounds the same way wherever it is encoded.
-// Decoding is binary16's.
+// spans the fixed spacing 2^-24 in steps of 2^-37.  The hash makes the
+// rounding reproducible: the same value rounds the same way wherever it is
+// encoded.  So the rounding is unbiased over the distinct values that occur,
+// not over time for one value: a value that recurs exactly rounds the same
+// way each time.  A population of a flow that changes at all changes its
+// bits, and with them its rounding, so the systematic error that rounding to
+// nearest leaves in nearly steady regions averages out.  All thirteen planes
+// are rounded this way (the flow populations need it too: rounded to nearest
+// they shift the mean flow of a long run).  Decoding is binary16's.
 struct CodecF16SR {
   using T = _Float16;
   static constexpr bool dev = true;
   __device__ static __forceinline__ float dec(T v, float off, float one) {
     return __builtin_fmaf((float)v, one, off);
   }
-  __device__ static __forceinline__ T enc(float v, float off, float one) {
+  __device__ static __forceinline__ T enc(float v, float off, float one, bool) {
     const float x = __builtin_fmaf(v, one, -off);
     const uint32_t xb = __builtin_bit_cast(uint32_t, x);
     // the lowbias32 mixer of C. Wellons' hash-prospector (its last xorshift
@@ -175,7 +181,7 @@ struct CodecBF16 {
   using T = __bf16;
   static constexpr bool dev = true;
   __device__ static __forceinline__ float dec(T v, float off, float) { return (float)v + off; }
-  __device__ static __forceinline__ T enc(float v, float off, float) { return (T)(v - off); }
+  __device__ static __forceinline__ T enc(float v, float off, float, bool) { return (T)(v - off); }
 };
 
 template <class C>
@@ -259,12 +265,8 @@ __device__ __forceinline__ bool collide(const JetDesc &d, float rinv, float r2,
     __builtin_amdgcn_sched_barrier(0);
   }
 
-  // equilibria (eq. 2 moments)
-  float feq[9], geq[4];
-#pragma unroll
-  for (int k = 0; k < 9; ++k) feq[k] = feq_link(k, rho, ux, ur);
-#pragma unroll
-  for (int k = 0; k < 4; ++k) geq[k] = geq_link(k, T, ux, ur);
+  // b of the equilibria (feq_link): 1 - 1.5 u.u
+  const float base = 1.0f - 1.5f * (ux * ux + ur * ur);
 
   // eq. (4): Q_ij = sum_k e_ki e_kj (f_k - f_k^eq), with the second moments of
   // the equilibrium in closed form: rho/3 delta_ij + rho u_i u_j
@@ -296,18 +298,36 @@ __device__ __forceinline__ bool collide(const JetDesc &d, float rinv, float r2,
   const float Fr = (-rho * ur * ur - kv * qrr) * rinv - 2.0f * rho * nu_tot * ur * hden;
   const float S = (-T * ur - ka * jr) * rinv;
 
-  // eq. (1), as f (1 - 1/tau) + f^eq / tau + source
+  // eq. (1), as f (1 - 1/tau) + f^eq / tau + source, relaxing opposite links
+  // together.  For k and k' = opp(k) (e_k' = -e_k) the equilibria share their
+  // even part w rho (b + 4.5 (e.u)^2) and differ in the sign of the odd part
+  // 3 w rho e.u; the sources likewise (w theta even, e.F / 6 odd):
+  //   f*_k = f_k (1 - 1/tau) + E + O,   f*_k' = f_k' (1 - 1/tau) + E - O,
+  //   E = w rho (b + 4.5 (e.u)^2) / tau + w theta,  O = 3 w rho (e.u) / tau + e.F / 6.
   const float fx6 = Fx * (1.0f / 6.0f), fr6 = Fr * (1.0f / 6.0f);
   const float omf = 1.0f - itau, omg = 1.0f - itau_a;
-#pragma unroll
-  for (int k = 0; k < 9; ++k)
-    f[k] = __builtin_fmaf(f[k], omf,
-                          __builtin_fmaf(feq[k], itau,
-                                         w9(k) * theta + proj(ex9(k), er9(k), fx6, fr6)));
-  const float s4 = 0.25f * S;
-#pragma unroll
-  for (int k = 0; k < 4; ++k)
-    g[k] = __builtin_fmaf(g[k], omg, __builtin_fmaf(geq[k], itau_a, s4));
+  const float rt = rho * itau;
+  const auto relax_pair = [&](int k, int kp, float w, float eu, float ef) {
+    const float cw = w * rt;
+    const float E = __builtin_fmaf(cw, __builtin_fmaf(4.5f * eu, eu, base), w * theta);
+    const float O = __builtin_fmaf(3.0f * cw, eu, ef);
+    f[k] = __builtin_fmaf(f[k], omf, E + O);
+    f[kp] = __builtin_fmaf(f[kp], omf, E - O);
+  };
+  f[0] = __builtin_fmaf(f[0], omf, __builtin_fmaf(w9(0) * rt, base, w9(0) * theta));
+  relax_pair(1, 3, w9(1), ux, fx6);                 // (+-1, 0)
+  relax_pair(2, 4, w9(2), ur, fr6);                 // (0, +-1)
+  relax_pair(5, 7, w9(5), ux + ur, fx6 + fr6);      // +-(1, 1)
+  relax_pair(6, 8, w9(6), ur - ux, fr6 - fx6);      // +-(-1, 1)
+  // D2Q4: g^eq_k / tau_a = T / (4 tau_a) + (e_k.u) T / (2 tau_a); the source
+  // S / 4 is even
+  const float cT = T * itau_a;
+  const float Eg = __builtin_fmaf(0.25f, cT, 0.25f * S);
+  const float hx = 0.5f * cT * ux, hr = 0.5f * cT * ur;
+  g[0] = __builtin_fmaf(g[0], omg, Eg + hx);  // +x
+  g[2] = __builtin_fmaf(g[2], omg, Eg - hx);  // -x
+  g[1] = __builtin_fmaf(g[1], omg, Eg + hr);  // +r
+  g[3] = __builtin_fmaf(g[3], omg, Eg - hr);  // -r
 
   return (rho > 0.0f) && (rho < __builtin_inff()) && (fabsf(T) < __builtin_inff());
 }
@@ -331,7 +351,8 @@ struct Dst {
   int64_t plane;
   int32_t pitch;
   __device__ __forceinline__ void put(const JetDesc &d, int p, int i, int j, float v) const {
-    base[(int64_t)p * plane + node_index(pitch, i, j)] = C::enc(v, pop_offset<C>(d, p), d.one);
+    base[(int64_t)p * plane + node_index(pitch, i, j)] =
+        C::enc(v, pop_offset<C>(d, p), d.one, p >= 9);
   }
 };
 
@@ -442,7 +463,7 @@ struct State {
     return C::dec(*at(p, i, j), pop_offset<C>(d, p), d.one);
   }
   __device__ __forceinline__ void put(const JetDesc &d, int p, int i, int j, float v) const {
-    *at(p, i, j) = C::enc(v, pop_offset<C>(d, p), d.one);
+    *at(p, i, j) = C::enc(v, pop_offset<C>(d, p), d.one, p >= 9);
   }
   __device__ __forceinline__ float pulled(const JetDesc &d, int p, int i, int j) const {
     const gptr<T> q = kind == 2 ? base + ((int64_t)p * plane + node_index(pitch, i, j))

@@ -158,7 +158,7 @@ __global__ __launch_bounds__(BX *BY) __attribute__((amdgpu_waves_per_eu(W, 8))) 
           VT v;
 #pragma unroll
           for (int e = 0; e < NX; ++e) {
-            const T x = C::enc(p < 9 ? f[e][p] : g[e][p - 9], off, d.one);
+            const T x = C::enc(p < 9 ? f[e][p] : g[e][p - 9], off, d.one, p >= 9);
             if constexpr (NX == 1) v = x; else v[e] = x;
           }
           buf_store<VB, (CP & 1) ? CACHE_NT : 0>(__builtin_bit_cast(typename Raw<VB>::type, v), rd,
@@ -172,7 +172,7 @@ __global__ __launch_bounds__(BX *BY) __attribute__((amdgpu_waves_per_eu(W, 8))) 
 #pragma unroll
             for (int p = 0; p < NPOP; ++p)
               o[(int64_t)p * d.plane + e] =
-                  C::enc(p < 9 ? f[e][p] : g[e][p - 9], pop_offset<C>(d, p), d.one);
+                  C::enc(p < 9 ? f[e][p] : g[e][p - 9], pop_offset<C>(d, p), d.one, p >= 9);
       }
       if (tile_edge) {
         const Dst<C> o{as_global(dst_raw), d.plane, d.pitch};
@@ -240,7 +240,7 @@ __device__ __forceinline__ void store_node(const JetDesc &d, __amdgpu_buffer_rsr
   constexpr int ES = (int)sizeof(T);
 #pragma unroll
   for (int p = 0; p < NPOP; ++p) {
-    const T x = C::enc(p < 9 ? f[p] : g[p - 9], pop_offset<C>(d, p), d.one);
+    const T x = C::enc(p < 9 ? f[p] : g[p - 9], pop_offset<C>(d, p), d.one, p >= 9);
     buf_store<ES, AUX>(__builtin_bit_cast(typename Raw<ES>::type, x), rd, voff,
                        (uint32_t)p * plane_b);
   }
@@ -262,7 +262,7 @@ constexpr int PAIR_W = 66;
 template <class C>
 __device__ __forceinline__ float storage_round(const JetDesc &d, int p, float v) {
   const float off = pop_offset<C>(d, p);
-  return C::dec(C::enc(v, off, d.one), off, d.one);
+  return C::dec(C::enc(v, off, d.one, p >= 9), off, d.one);
 }
 
 template <class C, int EH, int P0>
@@ -558,7 +558,7 @@ __global__ __launch_bounds__(256) void aa_kernel(
       const bool ok = collide(d, fast_rcp(rr), rr * rr, f, g);
 #pragma unroll
       for (int p = 0; p < NPOP; ++p) {
-        const T x = C::enc(p < 9 ? f[p] : g[p - 9], pop_offset<C>(d, p), d.one);
+        const T x = C::enc(p < 9 ? f[p] : g[p - 9], pop_offset<C>(d, p), d.one, p >= 9);
         const uint32_t soff =
             swapped ? (uint32_t)p * plane_b + (uint32_t)(per(p) * (int)pitch_b) +
                           (uint32_t)(pex(p) * ES)

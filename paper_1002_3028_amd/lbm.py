@@ -83,6 +83,7 @@ _SIGS = {
     "lbm_batch_admit": ([_vp, ctypes.POINTER(_Config), ctypes.c_int32, _dp, _dp, _dp,
                          ctypes.c_int64, ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
     "lbm_batch_run": ([_vp, ctypes.c_int32], ctypes.c_int),
+    "lbm_batch_wait": ([_vp, ctypes.c_int32], ctypes.c_int),
     "lbm_batch_poll": ([_vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "lbm_batch_profiles": ([_vp, ctypes.c_int32, _dp, _dp, _dp, _dp], ctypes.c_int),
     "lbm_batch_moments": ([_vp, ctypes.c_int32, _dp, _dp, _dp, _dp], ctypes.c_int),
@@ -405,6 +406,10 @@ class Batch:
 
     def run(self, k: int):
         _check(self.lib.lbm_batch_run(self.b, int(k)), "lbm_batch_run")
+
+    def wait(self, in_flight: int = 0):
+        """Wait until at most `in_flight` queued groups are unfinished."""
+        _check(self.lib.lbm_batch_wait(self.b, int(in_flight)), "lbm_batch_wait")
 
     def poll(self, slot: int) -> int:
         n = ctypes.c_int64()

@@ -7,6 +7,9 @@
   valu:    vector-ALU instructions executed per node update from a --pmc
            run of SQ_INSTS_VALU and SQ_WAVES (one instruction of a wave
            serves 64 lanes, so per update = total / (updates / 64)).
+  busy:    from a --kernel-trace run, the share of the traced span in which
+           some kernel runs (union of the dispatch intervals, so kernels on
+           several streams count once) and the idle gaps between kernels.
 
 Each writes a short text file that records the command which produced the
 figures and the SHA-256 of the kernel sources they were taken on.
@@ -117,8 +120,55 @@ def valu(args):
         f"valu_per_wave: {per_launch / statistics.median(waves):.1f}",
         f"node_updates_per_launch: {args.updates}",
         f"valu_per_node_update: {per_launch / (args.updates / 64):.1f}",
-        f"kernel_source_sha256: {kernel_source_sha256()}",
     ]
+    # wave-state counters, when the same pass collected them (per launch,
+    # medians): where a wave's life goes
+    extra = {}
+    for c in ("SQ_WAVE_CYCLES", "SQ_BUSY_CYCLES", "SQ_WAIT_INST_ANY", "SQ_ACTIVE_INST_VALU",
+              "SQ_INSTS_VMEM_RD", "SQ_INSTS_LDS"):
+        v = [x for k, vs in _per_kernel(args.csv, c).items() if args.kernel in k for x in vs]
+        if v:
+            extra[c] = statistics.median(v)
+            lines.append(f"{c.lower()}_per_launch: {extra[c]:.0f}")
+    if "SQ_WAVE_CYCLES" in extra:
+        wc = extra["SQ_WAVE_CYCLES"]
+        if "SQ_ACTIVE_INST_VALU" in extra:
+            lines.append(f"valu_issue_share_of_wave_cycles: {extra['SQ_ACTIVE_INST_VALU'] / wc:.3f}")
+        if "SQ_WAIT_INST_ANY" in extra:
+            lines.append(f"waiting_share_of_wave_cycles: {extra['SQ_WAIT_INST_ANY'] / wc:.3f}")
+        if "SQ_BUSY_CYCLES" in extra:
+            lines.append(f"mean_waves_in_flight_per_busy_cycle: {wc / extra['SQ_BUSY_CYCLES']:.1f}")
+    lines.append(f"kernel_source_sha256: {kernel_source_sha256()}")
+    with open(args.out, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def busy(args):
+    rows = [r for r in _rows(args.csv) if r.get("Kind", "KERNEL_DISPATCH") == "KERNEL_DISPATCH"]
+    iv = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in rows)
+    if args.skip:
+        iv = iv[args.skip:]
+    merged = []
+    for a, b in iv:
+        if merged and a <= merged[-1][1]:
+            merged[-1][1] = max(merged[-1][1], b)
+        else:
+            merged.append([a, b])
+    span = merged[-1][1] - merged[0][0]
+    run = sum(b - a for a, b in merged)
+    gaps = sorted(merged[q + 1][0] - merged[q][1] for q in range(len(merged) - 1))
+    big = [g for g in gaps if g > args.gap_us * 1000]
+    lines = [f"# GPU busy time from a kernel trace: {args.title}",
+             f"# command: {args.command}",
+             f"dispatches: {len(iv)}",
+             f"span_ms: {span / 1e6:.3f}",
+             f"busy_fraction: {run / span:.4f}",
+             f"gaps_over_{args.gap_us}us: {len(big)}",
+             f"idle_in_those_gaps_ms: {sum(big) / 1e6:.3f}",
+             f"median_gap_us: {statistics.median(gaps) / 1e3 if gaps else 0.0:.2f}",
+             f"largest_gap_us: {gaps[-1] / 1e3 if gaps else 0.0:.1f}",
+             f"kernel_source_sha256: {kernel_source_sha256()}"]
     with open(args.out, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -153,8 +203,15 @@ def main():
     c.add_argument("--out", required=True)
     c.add_argument("--title", required=True)
     c.add_argument("--command", required=True)
+    d = sub.add_parser("busy")
+    d.add_argument("--csv", required=True, help="kernel_trace.csv")
+    d.add_argument("--gap-us", type=float, default=20.0)
+    d.add_argument("--skip", type=int, default=0, help="leading dispatches to leave out")
+    d.add_argument("--out", required=True)
+    d.add_argument("--title", required=True)
+    d.add_argument("--command", required=True)
     args = ap.parse_args()
-    {"stats": stats, "traffic": traffic, "valu": valu}[args.cmd](args)
+    {"stats": stats, "traffic": traffic, "valu": valu, "busy": busy}[args.cmd](args)
 
 
 if __name__ == "__main__":

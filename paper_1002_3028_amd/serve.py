@@ -4,10 +4,12 @@ Requests (a jet configuration, its inlet rows and a step count) arrive over
 time.  A request is admitted as soon as it has arrived, a slot is free and
 its two population buffers fit the HBM budget; its populations stay resident
 on the device until it finishes.  All resident jets advance together, k
-steps per group, in one persistent launch per step.  After each group the
-jets that reached their step count return their centreline and exit-column
-profiles of u_x and T and free their slot and memory, so requests that
-arrived meanwhile join the next group.
+steps per group, in one persistent launch per step.  The loop queues each
+group before it handles the previous one, so the device is not left idle
+while the host works: the jets that reached their step count in the previous
+group return their centreline and exit-column profiles of u_x and T and free
+their slot and memory, and requests that arrived meanwhile are admitted and
+join the next group queued.
 
 Latency is completion minus arrival (wall clock); completion is taken when
 the device has finished the group in which the jet reached its step count.
@@ -19,6 +21,7 @@ from __future__ import annotations
 
 import argparse
 import collections
+import contextlib
 import json
 import math
 import time
@@ -32,84 +35,151 @@ def percentile(xs, q):
     return float(np.percentile(np.asarray(xs, dtype=np.float64), q)) if len(xs) else math.nan
 
 
+# Runs longer than this go from FP16 storage to FP16 with stochastic rounding
+# (route): rounding to nearest biases the temperature, whose profile error
+# grows linearly in time; it stays within 1 % up to 4 000 steps on the jets of
+# this workload (tests/test_gpu_run_length.py).
+FP16_STEP_LIMIT = 4000
+
+
+def route(precision: str, steps: int, long_after: int = FP16_STEP_LIMIT) -> str:
+    """The storage a request runs in: FP16 requests of more than `long_after`
+    steps run in FP16 with stochastic rounding (long_after = 0: never)."""
+    if precision == "fp16" and long_after and steps > long_after:
+        return "fp16sr"
+    return precision
+
+
 def serve(requests, precision: str = "fp16", budget_bytes: int = 16 << 30,
           max_slots: int = 256, k_steps: int = 100, realtime: bool = True,
           tile_shape: int = -1, workgroups: int = 0, keep_profiles: bool = False,
-          layout: str = "two", streams: int = 0, cohort_bytes: int = -1):
+          layout: str = "two", streams: int = 0, cohort_bytes: int = -1,
+          long_after: int = FP16_STEP_LIMIT, pipeline: bool = True):
     """Run the request list [(arrival_s, params, inlet, steps), ...].
     layout="single" keeps each resident jet in one buffer updated in place,
     so a budget holds twice as many jets.
 
+    Requests run in `precision`, except that with FP16 storage those of more
+    than `long_after` steps run in FP16 with stochastic rounding (route); each
+    storage form has its own batch, the budget and the slot count bound them
+    together, and all batches advance together.
+
     realtime=False admits every request at t = 0 (saturation: measures the
-    capacity).  streams (1 to 4) and cohort_bytes override the batch's
+    capacity).  pipeline=False waits for each group before the host retires
+    and admits (the device idles meanwhile).  streams (1 to 4) and cohort_bytes override the batch's
     defaults when given.  Returns a summary dict, plus per-request records.
     """
     order = sorted(range(len(requests)), key=lambda q: requests[q][0])
     pending = collections.deque(order)
-    live = {}  # slot -> request index
+    live = {}  # (storage, slot) -> request index
     rec = [None] * len(requests)
     updates = 0
     groups = 0
     peak_slots = 0
     peak_bytes = 0
-    with lbm.Batch(budget_bytes, max_slots, precision, layout=layout) as b:
-        b.set_launch(tile_shape, workgroups)
-        if streams:
-            b.set_streams(streams)
-        if cohort_bytes >= 0:
-            b.set_cohort_bytes(cohort_bytes)
+    precs = sorted({route(precision, r[3], long_after) for r in requests})
+    with contextlib.ExitStack() as stack:
+        batches = {}
+        for pr in precs:
+            b = stack.enter_context(lbm.Batch(budget_bytes, max_slots, pr, layout=layout))
+            b.set_launch(tile_shape, workgroups)
+            if streams:
+                b.set_streams(streams)
+            if cohort_bytes >= 0:
+                b.set_cohort_bytes(cohort_bytes)
+            batches[pr] = b
         t0 = time.perf_counter()
 
         def now():
             return time.perf_counter() - t0
 
-        while pending or live:
-            t = now()
-            while pending and (not realtime or requests[pending[0]][0] <= t):
-                q = pending[0]
-                arr, p, inlet, steps = requests[q]
-                rc, slot = b.try_admit(p, inlet, steps)
-                if rc == lbm.ENOMEM:
-                    break
-                if rc != lbm.OK:
-                    raise lbm.LbmError(rc, "lbm_batch_admit", lbm.strerror(rc))
-                live[slot] = q
-                pending.popleft()
-                rec[q] = {"arrival": arr if realtime else 0.0, "admitted": now(),
-                          "nodes": p["nx"] * p["nr"], "steps": steps}
-            n_act, used = b.active()
-            peak_slots = max(peak_slots, n_act)
-            peak_bytes = max(peak_bytes, used)
-            if not live:
-                if pending and realtime:
-                    time.sleep(max(0.0, min(requests[pending[0]][0] - now(), 0.01)))
-                continue
-            b.run(k_steps)
-            groups += 1
-            done = [s for s, q in live.items() if b.poll(s) >= rec[q]["steps"]]
-            b.sync()
-            t_done = now()
-            for s in done:
-                q = live.pop(s)
-                prof = b.profiles(s)
-                b.retire(s)
+        def finish(keys):
+            nonlocal updates
+            for key in keys:
+                q = live.pop(key)
+                prof = batches[key[0]].profiles(key[1])  # waits for the group it finished in
+                t_done = now()
+                batches[key[0]].retire(key[1])
                 rec[q]["completed"] = t_done
                 rec[q]["latency"] = t_done - rec[q]["arrival"]
                 updates += rec[q]["nodes"] * rec[q]["steps"]
                 if keep_profiles:
                     rec[q]["profiles"] = prof
+
+        finished_prev = []  # (storage, slot) of jets that finished in the last group queued
+        host = collections.Counter()  # host seconds by phase
+        while pending or live:
+            t = now()
+            while pending and (not realtime or requests[pending[0]][0] <= t):
+                q = pending[0]
+                arr, p, inlet, steps = requests[q]
+                pr = route(precision, steps, long_after)
+                if len(batches) > 1:  # the budget and slots bound all batches together
+                    act = [b.active() for b in batches.values()]
+                    if (sum(a[0] for a in act) >= max_slots or
+                            sum(a[1] for a in act) + batches[pr].jet_bytes(p) > budget_bytes):
+                        break
+                rc, slot = batches[pr].try_admit(p, inlet, steps)
+                if rc == lbm.ENOMEM:
+                    break
+                if rc != lbm.OK:
+                    raise lbm.LbmError(rc, "lbm_batch_admit", lbm.strerror(rc))
+                live[(pr, slot)] = q
+                pending.popleft()
+                rec[q] = {"arrival": arr if realtime else 0.0, "admitted": now(),
+                          "nodes": p["nx"] * p["nr"], "steps": steps, "storage": pr}
+            act = [b.active() for b in batches.values()]
+            peak_slots = max(peak_slots, sum(a[0] for a in act))
+            peak_bytes = max(peak_bytes, sum(a[1] for a in act))
+            running = [k for k, q in live.items() if batches[k[0]].poll(k[1]) < rec[q]["steps"]]
+            t1 = now()
+            host["admit"] += t1 - t
+            if running:
+                # queue the next group first: the device runs it while the
+                # host retires the jets of the previous group and admits
+                ran = sorted({k[0] for k in running})
+                for pr in ran:
+                    batches[pr].run(k_steps)
+                t2 = now()
+                for pr in ran:
+                    # the previous group (this one runs on), or this one when
+                    # not pipelined
+                    batches[pr].wait(1 if pipeline else 0)
+                t3 = now()
+                groups += 1
+                finish(finished_prev)
+                finished_prev = [k for k in running
+                                 if batches[k[0]].poll(k[1]) >= rec[live[k]]["steps"]]
+                if not pipeline:
+                    finish(finished_prev)
+                    finished_prev = []
+                host["run"] += t2 - t1
+                host["wait"] += t3 - t2
+                host["finish"] += now() - t3
+            else:
+                finish(finished_prev + [k for k in live if k not in finished_prev])
+                finished_prev = []
+                if pending and realtime:
+                    time.sleep(max(0.0, min(requests[pending[0]][0] - now(), 0.01)))
         t_end = now()
     lat = [r["latency"] for r in rec]
     first = min(r["arrival"] for r in rec)
     summary = {
         "requests": len(requests), "precision": precision, "realtime": realtime,
+        "pipeline": pipeline,
+        "storage_counts": dict(collections.Counter(r["storage"] for r in rec)),
         "k_steps": k_steps, "groups": groups,
         "p50_s": round(percentile(lat, 50), 4), "p99_s": round(percentile(lat, 99), 4),
+        # arrival to admission (queueing for memory or slots, and the group in flight)
+        "admit_wait_p99_s": round(percentile([r["admitted"] - r["arrival"] for r in rec], 99), 4),
         "mean_s": round(float(np.mean(lat)), 4),
         "wall_s": round(t_end - first, 3),
         "requests_per_s": round(len(requests) / (t_end - first), 3),
         "glups": round(updates / (t_end - first) / 1e9, 3),
         "peak_slots": peak_slots, "peak_bytes": peak_bytes, "budget_bytes": budget_bytes,
+        # host time per group, by phase: admitting, queueing the group, waiting
+        # for the previous one, retiring the jets it finished
+        "host_ms_per_group": {k: round(v / max(groups, 1) * 1e3, 3) for k, v in host.items()},
     }
     return summary, rec
 
@@ -131,6 +201,11 @@ def main():
     ap.add_argument("--sweep", default="",
                     help="comma-separated fractions of the measured capacity to run at "
                          "(e.g. 0.3,0.5,0.7,0.9); overrides --rate")
+    ap.add_argument("--sync", action="store_true",
+                    help="wait for each group before retiring and admitting")
+    ap.add_argument("--long-after", type=int, default=FP16_STEP_LIMIT,
+                    help="FP16 requests of more steps run in FP16 with stochastic "
+                         "rounding (0: never)")
     args = ap.parse_args()
     budget = int(args.budget_gb * (1 << 30))
     cohort = args.cohort_mib << 20 if args.cohort_mib >= 0 else -1
@@ -139,7 +214,8 @@ def main():
     if rate <= 0 or args.sweep:
         cap, _ = serve(inputs.arrival_trace(args.requests, args.seed, rate=1.0), args.precision,
                        budget, args.slots, args.k, realtime=False, layout=args.layout,
-                       streams=args.streams, cohort_bytes=cohort)
+                       streams=args.streams, cohort_bytes=cohort, long_after=args.long_after,
+                       pipeline=not args.sync)
         print(json.dumps({"saturated": cap}), flush=True)
     fractions = [float(x) for x in args.sweep.split(",") if x] if args.sweep else [None]
     for frac in fractions:
@@ -149,7 +225,8 @@ def main():
             rate = 0.7 * cap["requests_per_s"]
         trace = inputs.arrival_trace(args.requests, args.seed, rate=rate)
         summary, _ = serve(trace, args.precision, budget, args.slots, args.k, realtime=True,
-                           layout=args.layout, streams=args.streams, cohort_bytes=cohort)
+                           layout=args.layout, streams=args.streams, cohort_bytes=cohort,
+                           long_after=args.long_after, pipeline=not args.sync)
         summary["rate"] = rate
         if frac is not None:
             summary["fraction_of_capacity"] = frac

@@ -59,3 +59,26 @@ def test_budget_limits_concurrency():
                                k_steps=10, realtime=False)
     assert summary["peak_slots"] == 2
     assert all(r["latency"] > 0 for r in rec)
+
+
+def test_long_requests_route_to_stochastic_rounding():
+    """With FP16 storage, requests longer than the step limit run in their own
+    FP16SR batch; every result equals its alone run in the storage it was
+    routed to, and the budget and slot count bound both batches together."""
+    from paper_1002_3028_amd import lbm, serve
+    trace = _small_trace()
+    limit = int(np.median([t[3] for t in trace]))
+    summary, rec = serve.serve(trace, "fp16", budget_bytes=64 << 20, max_slots=6,
+                               k_steps=20, realtime=True, keep_profiles=True, long_after=limit)
+    counts = summary["storage_counts"]
+    assert counts.get("fp16sr", 0) > 0 and counts.get("fp16", 0) > 0, counts
+    assert summary["peak_slots"] <= 6 and summary["peak_bytes"] <= 64 << 20
+    for q, (arr, p, inlet, steps) in enumerate(trace):
+        want = "fp16sr" if steps > limit else "fp16"
+        assert rec[q]["storage"] == want
+        with lbm.Batch(1 << 26, 1, want) as alone:
+            s = alone.admit(p, inlet, steps)
+            alone.run(steps)
+            prof = alone.profiles(s)
+        for key in prof:
+            assert np.array_equal(prof[key], rec[q]["profiles"][key]), (q, key)

@@ -34,3 +34,15 @@ def test_noise_is_seeded():
     c = inputs.perturbed_state(30, 10, seed=4, noise=0.3)
     assert all(np.array_equal(x, y) for x, y in zip(a, b))
     assert not np.array_equal(a[0], c[0])
+
+
+def test_serving_route():
+    """Only FP16 requests longer than the step limit change storage; 0 turns
+    routing off."""
+    from paper_1002_3028_amd import serve
+    lim = serve.FP16_STEP_LIMIT
+    assert serve.route("fp16", lim) == "fp16"
+    assert serve.route("fp16", lim + 1) == "fp16sr"
+    assert serve.route("fp16", 10 * lim, long_after=0) == "fp16"
+    for prec in ("fp32", "bf16", "fp16sr"):
+        assert serve.route(prec, 10 * lim) == prec

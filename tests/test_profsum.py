@@ -117,3 +117,23 @@ def test_bench_graph_group_divides_the_timed_steps(steps, group):
     g = bench.graph_group(steps)
     assert g == group
     assert g % 2 == 0 and (steps % g == 0 or g == 50)
+
+
+def test_busy_counts_overlapping_kernels_once(tmp_path):
+    """Two streams' kernels overlap: the busy time is the union of the
+    intervals, and only the idle stretch between them is a gap."""
+    rows = [("KERNEL_DISPATCH", 0, 100), ("KERNEL_DISPATCH", 50, 150),   # overlap
+            ("KERNEL_DISPATCH", 150, 200),                                # touching
+            ("KERNEL_DISPATCH", 60_200, 60_300)]                          # after a 60 us gap
+    path = tmp_path / "k.csv"
+    with open(path, "w", newline="") as fh:
+        w = csv.writer(fh)
+        w.writerow(["Kind", "Start_Timestamp", "End_Timestamp"])
+        w.writerows(rows)
+    out = tmp_path / "b.txt"
+    _run(["busy", "--csv", str(path), "--gap-us", "20", "--out", str(out), "--title", "t",
+          "--command", "c"])
+    v = _vals(out)
+    assert float(v["busy_fraction"]) == pytest.approx(300 / 60_300, abs=1e-4)
+    assert int(v["gaps_over_20.0us"]) == 1
+    assert float(v["largest_gap_us"]) == pytest.approx(60.0)
