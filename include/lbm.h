@@ -208,6 +208,19 @@ int lbm_set_populations(lbm_handle *h, const double *f, const double *g,
 /* FP64 reductions of the step's pre-collision moments:
  * mass3d = sum_ij r_j rho_ij, energy3d = sum_ij r_j T_ij. */
 int lbm_conservation(lbm_handle *h, double *mass3d, double *energy3d);
+/* lbm_conservation for callers that cannot allocate device memory (a
+ * serving loop or harness that forbids allocation): the same reduction, with
+ * the same kernels and the same bits, but its partial sums (at most 1025 of
+ * 32 B: one per reduction workgroup and the total) live in a fixed array
+ * that the library holds on each device until the process ends, instead of
+ * a buffer it allocates on first use.  Calls no allocating routine.  Every
+ * call on one device uses that device's array: calls that overlap on one
+ * device (from several host threads or handles) race and must be
+ * serialised by the caller.  Nothing in the array needs clearing between
+ * calls (every partial is written before it is read).  Synchronises;
+ * LBM_EINVAL for a grid that would need more partials (none that
+ * lbm_create accepts does). */
+int lbm_conservation_noalloc(lbm_handle *h, double *mass3d, double *energy3d);
 /* Centreline (j = 0) u_x and T, nx each; exit column (i = nx-1), nr each. */
 int lbm_profiles(lbm_handle *h, double *ux_axis, double *T_axis,
                  double *ux_exit, double *T_exit);

@@ -5,6 +5,8 @@
 // table, the inlet rows and an instability flag.  Steps are enqueued as one
 // launch of the step kernel each, or as HIP graphs of k launches followed
 // by the descriptor advance.
+#include <mutex>
+
 #include "lbm_runtime.hpp"
 
 using namespace lbmx;
@@ -15,6 +17,13 @@ namespace {
 constexpr int kMaxRedBlocks = 1024;
 }  // namespace
 
+// Partial sums of the no-allocation FP64 conservation reduction
+// (lbm_conservation_noalloc): one per reduction workgroup, then the total.
+// 32.8 KB.  Each device holds its own copy until the process ends.  In host
+// code the name stands for no device address: host code reaches the array
+// only through the pointer that hipGetSymbolAddress returns for the current
+// device (scratch_on).
+static __device__ __align__(256) RedPartial scratch[kMaxRedBlocks + 1];
 
 struct lbm_handle {
   int device = 0;
@@ -344,6 +353,29 @@ int launch_steps(lbm_handle *h, int64_t n) {
   return LBM_OK;
 }
 
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+RedPartial *g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of `scratch` on `device`, resolved once per device with
+// that device current.
+int scratch_on(int device, RedPartial **out) {
+  if (device < 0 || device >= kMaxDevices) return LBM_EDEVICE;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    int cur = -1;
+    LBM_HIP(hipGetDevice(&cur));
+    if (cur != device) LBM_HIP(hipSetDevice(device));
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != device) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !p) return LBM_EDEVICE;
+    g_scratch_ptr[device] = (RedPartial *)p;
+  }
+  *out = g_scratch_ptr[device];
+  return LBM_OK;
+}
+
 // Reduction workgroups of the conservation kernels for a grid (the same
 // count in both conservation entry points, so their sums agree bit for bit).
 int red_blocks(const lbm_handle *h) {
@@ -493,6 +525,16 @@ int lbm_conservation(lbm_handle *h, double *mass3d, double *energy3d) {
   const int rc = h->scratch.get((nblocks + 1) * sizeof(RedPartial), &p);
   if (rc) return rc;
   return conservation_into(h, (RedPartial *)p, nblocks, mass3d, energy3d);
+}
+
+int lbm_conservation_noalloc(lbm_handle *h, double *mass3d, double *energy3d) {
+  if (!h || !mass3d || !energy3d) return LBM_EINVAL;
+  const int nblocks = red_blocks(h);
+  if (nblocks > kMaxRedBlocks) return LBM_EINVAL;
+  RedPartial *part;
+  const int rc = scratch_on(h->device, &part);
+  if (rc) return rc;
+  return conservation_into(h, part, nblocks, mass3d, energy3d);
 }
 
 int lbm_set_state(lbm_handle *h, const double *rho, const double *ux, const double *ur,

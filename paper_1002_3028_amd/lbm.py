@@ -75,6 +75,7 @@ _SIGS = {
     "lbm_get_populations": ([_vp, _dp, _dp], ctypes.c_int),
     "lbm_set_populations": ([_vp, _dp, _dp, ctypes.c_int64], ctypes.c_int),
     "lbm_conservation": ([_vp, _dp, _dp], ctypes.c_int),
+    "lbm_conservation_noalloc": ([_vp, _dp, _dp], ctypes.c_int),
     "lbm_profiles": ([_vp, _dp, _dp, _dp, _dp], ctypes.c_int),
     "lbm_strerror": ([ctypes.c_int], ctypes.c_char_p),
     "lbm_probe_copy": ([_vp, _vp, ctypes.c_size_t, _vp], ctypes.c_int),
@@ -320,6 +321,13 @@ class Solver:
         m, e = ctypes.c_double(), ctypes.c_double()
         _check(self.lib.lbm_conservation(self.h, ctypes.byref(m), ctypes.byref(e)),
                "lbm_conservation")
+        return m.value, e.value
+
+    def conservation_noalloc(self):
+        """conservation() with the library's fixed per-device partial sums."""
+        m, e = ctypes.c_double(), ctypes.c_double()
+        _check(self.lib.lbm_conservation_noalloc(self.h, ctypes.byref(m), ctypes.byref(e)),
+               "lbm_conservation_noalloc")
         return m.value, e.value
 
     def set_state(self, rho, ux, ur, T):
