@@ -39,11 +39,36 @@ def _rows(path):
         return list(csv.DictReader(fh))
 
 
+def _window_stats(trace_csv, kernel, last):
+    """Per-kernel rows (as in a --stats table) over the tail of a kernel trace
+    that starts with the first of the last `last` dispatches of `kernel`:
+    the timed region of a run, without its set-up and tuning launches."""
+    rows = [r for r in _rows(trace_csv) if r.get("Kind", "KERNEL_DISPATCH") == "KERNEL_DISPATCH"]
+    rows.sort(key=lambda r: int(r["Start_Timestamp"]))
+    mine = [q for q, r in enumerate(rows) if kernel in r["Kernel_Name"]]
+    if len(mine) < last:
+        raise SystemExit(f"{len(mine)} dispatches of {kernel!r}, fewer than {last}")
+    per = {}
+    for r in rows[mine[-last]:]:
+        per.setdefault(r["Kernel_Name"], []).append(
+            int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+    total = sum(sum(v) for v in per.values())
+    out = [{"Name": k, "Calls": len(v), "AverageNs": sum(v) / len(v), "MinNs": min(v),
+            "MaxNs": max(v), "Percentage": 100.0 * sum(v) / total} for k, v in per.items()]
+    return sorted(out, key=lambda r: -r["Percentage"])
+
+
 def stats(args):
-    rows = _rows(args.csv)
+    if args.trace:
+        rows = _window_stats(args.trace, args.kernel, args.last)
+    else:
+        rows = _rows(args.csv)
     lines = [f"# rocprofv3 kernel statistics: {args.title}",
-             f"# command: {args.command}",
-             "# kernel | calls | average us | min us | max us | share %"]
+             f"# command: {args.command}"]
+    if args.trace:
+        lines.append(f"# from the kernel trace, over the last {args.last} dispatches of "
+                     f"{args.kernel} and everything after the first of them")
+    lines.append("# kernel | calls | average us | min us | max us | share %")
     for r in rows[: args.top]:
         name = r["Name"]
         if len(name) > 110:
@@ -178,7 +203,11 @@ def main():
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
     a = sub.add_parser("stats")
-    a.add_argument("--csv", required=True)
+    a.add_argument("--csv", help="kernel_stats.csv")
+    a.add_argument("--trace", help="kernel_trace.csv: tabulate a window of it instead")
+    a.add_argument("--kernel", help="with --trace: substring of the timed kernel's name")
+    a.add_argument("--last", type=int, default=0,
+                   help="with --trace: the timed kernel's dispatches in the window")
     a.add_argument("--out", required=True)
     a.add_argument("--title", required=True)
     a.add_argument("--command", required=True)
@@ -211,6 +240,8 @@ def main():
     d.add_argument("--title", required=True)
     d.add_argument("--command", required=True)
     args = ap.parse_args()
+    if args.cmd == "stats" and not (args.csv or (args.trace and args.kernel and args.last > 0)):
+        ap.error("stats needs --csv, or --trace with --kernel and --last")
     {"stats": stats, "traffic": traffic, "valu": valu, "busy": busy}[args.cmd](args)
 
 

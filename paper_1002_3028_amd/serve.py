@@ -42,11 +42,12 @@ def percentile(xs, q):
 FP16_STEP_LIMIT = 4000
 
 
-def route(precision: str, steps: int, long_after: int = FP16_STEP_LIMIT) -> str:
+def route(precision: str, steps: int, long_after: int = FP16_STEP_LIMIT,
+          long_storage: str = "fp16sr") -> str:
     """The storage a request runs in: FP16 requests of more than `long_after`
-    steps run in FP16 with stochastic rounding (long_after = 0: never)."""
+    steps run in `long_storage` (long_after = 0: never)."""
     if precision == "fp16" and long_after and steps > long_after:
-        return "fp16sr"
+        return long_storage
     return precision
 
 
@@ -54,13 +55,14 @@ def serve(requests, precision: str = "fp16", budget_bytes: int = 16 << 30,
           max_slots: int = 256, k_steps: int = 100, realtime: bool = True,
           tile_shape: int = -1, workgroups: int = 0, keep_profiles: bool = False,
           layout: str = "two", streams: int = 0, cohort_bytes: int = -1,
-          long_after: int = FP16_STEP_LIMIT, pipeline: bool = True):
+          long_after: int = FP16_STEP_LIMIT, long_storage: str = "fp16sr",
+          pipeline: bool = True):
     """Run the request list [(arrival_s, params, inlet, steps), ...].
     layout="single" keeps each resident jet in one buffer updated in place,
     so a budget holds twice as many jets.
 
     Requests run in `precision`, except that with FP16 storage those of more
-    than `long_after` steps run in FP16 with stochastic rounding (route); each
+    than `long_after` steps run in `long_storage` (route); each
     storage form has its own batch, the budget and the slot count bound them
     together, and all batches advance together.
 
@@ -77,7 +79,7 @@ def serve(requests, precision: str = "fp16", budget_bytes: int = 16 << 30,
     groups = 0
     peak_slots = 0
     peak_bytes = 0
-    precs = sorted({route(precision, r[3], long_after) for r in requests})
+    precs = sorted({route(precision, r[3], long_after, long_storage) for r in requests})
     with contextlib.ExitStack() as stack:
         batches = {}
         for pr in precs:
@@ -113,7 +115,7 @@ def serve(requests, precision: str = "fp16", budget_bytes: int = 16 << 30,
             while pending and (not realtime or requests[pending[0]][0] <= t):
                 q = pending[0]
                 arr, p, inlet, steps = requests[q]
-                pr = route(precision, steps, long_after)
+                pr = route(precision, steps, long_after, long_storage)
                 if len(batches) > 1:  # the budget and slots bound all batches together
                     act = [b.active() for b in batches.values()]
                     if (sum(a[0] for a in act) >= max_slots or
@@ -204,8 +206,8 @@ def main():
     ap.add_argument("--sync", action="store_true",
                     help="wait for each group before retiring and admitting")
     ap.add_argument("--long-after", type=int, default=FP16_STEP_LIMIT,
-                    help="FP16 requests of more steps run in FP16 with stochastic "
-                         "rounding (0: never)")
+                    help="FP16 requests of more steps run in --long-storage (0: never)")
+    ap.add_argument("--long-storage", default="fp16sr", choices=["fp16sr", "fp32"])
     args = ap.parse_args()
     budget = int(args.budget_gb * (1 << 30))
     cohort = args.cohort_mib << 20 if args.cohort_mib >= 0 else -1
@@ -215,7 +217,7 @@ def main():
         cap, _ = serve(inputs.arrival_trace(args.requests, args.seed, rate=1.0), args.precision,
                        budget, args.slots, args.k, realtime=False, layout=args.layout,
                        streams=args.streams, cohort_bytes=cohort, long_after=args.long_after,
-                       pipeline=not args.sync)
+                       long_storage=args.long_storage, pipeline=not args.sync)
         print(json.dumps({"saturated": cap}), flush=True)
     fractions = [float(x) for x in args.sweep.split(",") if x] if args.sweep else [None]
     for frac in fractions:
@@ -226,7 +228,8 @@ def main():
         trace = inputs.arrival_trace(args.requests, args.seed, rate=rate)
         summary, _ = serve(trace, args.precision, budget, args.slots, args.k, realtime=True,
                            layout=args.layout, streams=args.streams, cohort_bytes=cohort,
-                           long_after=args.long_after, pipeline=not args.sync)
+                           long_after=args.long_after,
+                           long_storage=args.long_storage, pipeline=not args.sync)
         summary["rate"] = rate
         if frac is not None:
             summary["fraction_of_capacity"] = frac

@@ -137,3 +137,33 @@ def test_busy_counts_overlapping_kernels_once(tmp_path):
     assert float(v["busy_fraction"]) == pytest.approx(300 / 60_300, abs=1e-4)
     assert int(v["gaps_over_20.0us"]) == 1
     assert float(v["largest_gap_us"]) == pytest.approx(60.0)
+
+
+def test_stats_window_of_a_trace(tmp_path, monkeypatch):
+    """stats --trace tabulates only the tail that starts at the first of the
+    kernel's last N dispatches: the tuning launches before it (and their
+    short dry runs) stay out of the average bench.py compares with."""
+    rows = [("tune_kernel", 0, 5), ("pair_kernel", 10, 12),        # a dry replay
+            ("pair_kernel", 20, 40), ("pair_kernel", 50, 70),
+            ("advance_kernel", 70, 74), ("pair_kernel", 80, 110)]
+    path = tmp_path / "t.csv"
+    with open(path, "w", newline="") as fh:
+        w = csv.writer(fh)
+        w.writerow(["Kind", "Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        w.writerows([("KERNEL_DISPATCH",) + r for r in rows])
+    out = tmp_path / "s.txt"
+    _run(["stats", "--trace", str(path), "--kernel", "pair_kernel", "--last", "3",
+          "--out", str(out), "--title", "t", "--command", "c"])
+    from paper_1002_3028_amd import profsum
+    lines = [ln.split("|") for ln in open(out) if ln.count("|") == 5 and not ln.startswith("#")]
+    table = {c[0].strip(): [x.strip() for x in c[1:]] for c in lines}
+    assert set(table) == {"pair_kernel", "advance_kernel"}
+    assert table["pair_kernel"][0] == "3"
+    assert float(table["pair_kernel"][1]) == pytest.approx(70 / 3 / 1e3, abs=1e-3)
+    assert float(table["advance_kernel"][1]) == pytest.approx(0.004)
+    import bench
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    os.makedirs(tmp_path / "profiles", exist_ok=True)
+    os.replace(out, tmp_path / "profiles" / "s.txt")
+    assert bench.read_trace_us("s.txt", "pair_kernel") == pytest.approx(0.023, abs=1e-3)
+    assert profsum.kernel_source_sha256() in open(tmp_path / "profiles" / "s.txt").read()
