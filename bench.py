@@ -44,9 +44,11 @@ CODEC = {"fp32": "CodecF32", "fp16": "CodecF16", "bf16": "CodecBF16", "fp16sr": 
 # instruction every 4 cycles per SIMD; packed FP32 not used), lane-ops/s.
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # VALU instructions in the collision of one FP32 node update as compiled for
-# gfx950 (eqs. 2-6 and 1 from the pulled values to the relaxed ones; the
-# counters' executed figure per kernel is read from profiles/valu_*.txt).
-VALU_COLLISION = 185
+# gfx950 (eqs. 2-6 and 1 from the pulled values to the relaxed ones): the
+# static count of a kernel that loads a node's 13 values, collides and stores
+# them, less that of the same kernel without the collision.  The counters'
+# executed figure per kernel is read from profiles/valu_*.txt.
+VALU_COLLISION = 166
 
 
 def log(msg):
@@ -162,18 +164,23 @@ def time_jet(params, inlet, precision, steps, warmup, check_every=1000, tile_sha
             s.conservation()
             costs.append(time.perf_counter() - t)
         check_s = sorted(costs)[1]
+        # the timing events, one pair per window between checks, exist before
+        # the clock starts (a first record creates the device event, a host
+        # call of several microseconds)
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(-(-steps // check_every))]
+        for e0, e1 in evs:
+            e0.record(s.torch_stream)
+            e1.record(s.torch_stream)
         s.step(warmup)
         torch.cuda.synchronize()
-        evs = []
         t0 = time.perf_counter()
         done = 0
-        while done < steps:
+        for e0, e1 in evs:
             n = min(check_every, steps - done)
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(s.torch_stream)
             s.step(n)
             e1.record(s.torch_stream)
-            evs.append((e0, e1))
             done += n
             if n == check_every:
                 s.conservation()  # FP64 reduction + stability check (syncs)

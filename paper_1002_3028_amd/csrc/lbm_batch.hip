@@ -336,12 +336,21 @@ int lbm_batch_create(size_t budget_bytes, int32_t max_slots, int32_t precision,
             hipHostMalloc(&b->h_slot, max_slots * sizeof(JetDesc), hipHostMallocDefault) ==
                 hipSuccess &&
             hipHostMalloc(&b->h_zero, sizeof(int32_t), hipHostMallocDefault) == hipSuccess;
+  // The runtime spreads a process's streams over a few hardware queues (four
+  // by default), and work on streams that share a queue runs in submission
+  // order.  The batch's own streams are created back to back -- the cohort
+  // streams first, then extraction and capture -- so that they land on
+  // distinct queues: with a caller's stream, or with other streams created in
+  // between, the second cohort stream shared the first one's queue in one
+  // batch out of two, and the cohorts ran one after the other.
   if (ok && hip_stream) {
     b->stream = (hipStream_t)hip_stream;
   } else if (ok) {
     ok = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) == hipSuccess;
     b->own_stream = ok;
   }
+  // the second cohort stream of the default two; one stream if it cannot be had
+  if (ok && lbm_batch_set_streams(b, 2) != LBM_OK) b->nstreams = 1;
   ok = ok && hipStreamCreateWithFlags(&b->io, hipStreamNonBlocking) == hipSuccess &&
        hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) == hipSuccess &&
        hipEventCreateWithFlags(&b->mark, hipEventDisableTiming) == hipSuccess;
@@ -366,8 +375,6 @@ int lbm_batch_create(size_t budget_bytes, int32_t max_slots, int32_t precision,
     return LBM_ENOMEM;
   }
   b->arena.reset(b->budget);
-  // the second stream of the default two; one stream if it cannot be had
-  if (lbm_batch_set_streams(b, 2) != LBM_OK) b->nstreams = 1;
   *out = b;
   return LBM_OK;
 }

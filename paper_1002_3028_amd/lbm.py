@@ -353,15 +353,16 @@ class Batch:
 
     def __init__(self, budget_bytes: int, max_slots: int, precision: str = "fp32", stream=None,
                  layout: str = "two"):
-        import torch
-
         lib = load()
         self.lib = lib
         self.precision = precision
-        self.torch_stream = stream if stream is not None else torch.cuda.Stream()
+        # without a caller's stream the library creates its own streams, back
+        # to back, so that they sit on distinct hardware queues
+        self.torch_stream = stream
         b = _vp()
         _check(lib.lbm_batch_create(int(budget_bytes), int(max_slots), PRECISION[precision],
-                                    _vp(self.torch_stream.cuda_stream), ctypes.byref(b)),
+                                    _vp(stream.cuda_stream) if stream is not None else None,
+                                    ctypes.byref(b)),
                "lbm_batch_create")
         self.b = b
         self.shapes = {}
