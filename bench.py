@@ -274,12 +274,15 @@ def bench_batch(n_jets=64, steps=5000, precision="fp32"):
 
 def bench_serving(n_requests=2000):
     """The serving workload (Poisson trace of seed 3): saturated capacity of
-    FP32 and FP16 storage (every request admitted at once), then both
-    storages on the same trace at one arrival rate, 0.7 x the FP32
-    capacity: p50/p99 latency (arrival to completion) and throughput."""
+    FP32 and FP16 storage (every request admitted at once), then the same
+    trace at one arrival rate, 0.7 x the FP32 capacity: p50/p99 latency
+    (arrival to completion) and throughput.  FP16 as served by default
+    routes requests longer than the FP16 step limit to FP16 with stochastic
+    rounding (serve.route); "fp16_unrouted" keeps every request in FP16."""
     from paper_1002_3028_amd import inputs, serve
 
-    out = {"requests": n_requests, "trace_seed": 3}
+    out = {"requests": n_requests, "trace_seed": 3,
+           "fp16_step_limit": serve.FP16_STEP_LIMIT}
     cap = {}
     for prec in ("fp32", "fp16"):
         log(f"serving {prec}: capacity, {n_requests} requests")
@@ -288,13 +291,16 @@ def bench_serving(n_requests=2000):
         cap[prec] = c
         out[f"{prec}_capacity_req_per_s"] = c["requests_per_s"]
         out[f"{prec}_capacity_glups"] = c["glups"]
+    out["fp16_storage_counts"] = cap["fp16"]["storage_counts"]
     rate = 0.7 * cap["fp32"]["requests_per_s"]
     out["rate_req_per_s"] = round(rate, 3)
     trace = inputs.arrival_trace(n_requests, 3, rate=rate)
-    for prec in ("fp32", "fp16"):
-        log(f"serving {prec}: {rate:.1f} requests/s")
-        run, _ = serve.serve(trace, prec, 16 << 30, 256, 100, realtime=True)
-        out[prec] = {"p50_s": run["p50_s"], "p99_s": run["p99_s"], "mean_s": run["mean_s"],
+    for name, prec, long_after in (("fp32", "fp32", 0), ("fp16", "fp16", serve.FP16_STEP_LIMIT),
+                                   ("fp16_unrouted", "fp16", 0)):
+        log(f"serving {name}: {rate:.1f} requests/s")
+        run, _ = serve.serve(trace, prec, 16 << 30, 256, 100, realtime=True,
+                             long_after=long_after)
+        out[name] = {"p50_s": run["p50_s"], "p99_s": run["p99_s"], "mean_s": run["mean_s"],
                      "served_req_per_s": run["requests_per_s"], "glups": run["glups"],
                      "peak_slots": run["peak_slots"]}
     return out

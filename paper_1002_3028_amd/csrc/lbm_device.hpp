@@ -116,8 +116,8 @@ struct RedPartial {
 // ---------------------------------------------------------------------------
 // Storage codecs.  FP32 stores populations as they are; the 16-bit codecs
 // store the deviation from a reference (w_k rho_ref for f, g_ref/4 for g).
-// enc(v, off, one, thermal): `thermal` is true for the four temperature
-// planes (g); no codec treats them differently at present.
+// enc(v, off, one, key): `key` is the population's rounding key (sr_key,
+// plane_key); only stochastic rounding uses it.
 // ---------------------------------------------------------------------------
 // `one` is 1.0f from the descriptor: with it the FP16 codec maps onto the
 // mixed-precision FMA (decode: h * 1 + offset in one instruction; encode: the
@@ -126,7 +126,7 @@ struct CodecF32 {
   using T = float;
   static constexpr bool dev = false;
   __device__ static __forceinline__ float dec(T v, float, float) { return v; }
-  __device__ static __forceinline__ T enc(float v, float, float, bool) { return v; }
+  __device__ static __forceinline__ T enc(float v, float, float, uint32_t) { return v; }
 };
 struct CodecF16 {
   using T = _Float16;
@@ -134,54 +134,76 @@ struct CodecF16 {
   __device__ static __forceinline__ float dec(T v, float off, float one) {
     return __builtin_fmaf((float)v, one, off);
   }
-  __device__ static __forceinline__ T enc(float v, float off, float one, bool) {
+  __device__ static __forceinline__ T enc(float v, float off, float one, uint32_t) {
     return (T)__builtin_fmaf(v, one, -off);
   }
 };
+// Rounding keys of stochastic rounding.  sr_key hashes a node's position
+// and the step of the state being written (the lowbias32 mixer of C.
+// Wellons' hash-prospector over (j << 16 | i) xor step * 2^32/phi; nx, nr
+// < 2^16); plane_key gives each population its own rotation of it.  Every
+// kernel that writes a population of node (i, j) for the state of step s
+// uses plane_key(sr_key(i, j, s), k), k the population's index (a ghost copy
+// of population k takes k's key, so that it equals the stored value), so the
+// two-step, single-buffer and batched paths round exactly as the one-step
+// kernel does.  Ghost values not produced by a step (the ghost fill, and the
+// constant ghosts of equilibrium sides) take the ghost position's key at
+// step 0.
+__device__ __forceinline__ uint32_t sr_key(int i, int j, int64_t step) {
+  uint32_t x = ((uint32_t)j << 16) | ((uint32_t)i & 0xffffu);
+  x ^= (uint32_t)step * 0x9e3779b9u;
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+__device__ __forceinline__ uint32_t plane_key(uint32_t key, int p) {
+  return __builtin_amdgcn_alignbit(key, key, (uint32_t)(7 * p) & 31u);
+}
+
 // binary16 deviations with stochastic rounding: the magnitude rounds toward
-// zero after adding r times its FP32 ulp, r in [0, 2^13) a hash of the value's
-// bits.  Where binary16 is normal its spacing is 2^13 FP32 ulps, the sum is
-// exact, and the value rounds up with exactly the probability of the discarded
-// fraction (values binary16 holds stay as they are); below 2^-14 the offset
-// spans the fixed spacing 2^-24 in steps of 2^-37.  The hash makes the
-// rounding reproducible: the same value rounds the same way wherever it is
-// encoded.  So the rounding is unbiased over the distinct values that occur,
-// not over time for one value: a value that recurs exactly rounds the same
-// way each time.  A population of a flow that changes at all changes its
-// bits, and with them its rounding, so the systematic error that rounding to
-// nearest leaves in nearly steady regions averages out.  All thirteen planes
-// are rounded this way (the flow populations need it too: rounded to nearest
-// they shift the mean flow of a long run).  Decoding is binary16's.
+// zero after adding r times its FP32 ulp, r in [0, 2^13) the top 13 bits of
+// the value's bits xor its rounding key.  Where binary16 is normal its
+// spacing is 2^13 FP32 ulps, the sum is exact, and over keys drawn uniformly
+// the value rounds up with exactly the probability of the discarded fraction
+// (whatever the value: xor with a uniform key makes r uniform); values
+// binary16 holds are stored unchanged.  Below 2^-14 the offset spans the
+// fixed spacing 2^-24 in steps of 2^-37.  The key changes with the node and
+// the step, so a value that recurs at one node rounds independently at every
+// step and the systematic error that rounding to nearest leaves in nearly
+// steady regions averages out.  Populations of one node with equal top bits
+// share the key's bits in part (rotations of one 32-bit key): their
+// roundings are correlated but each is unbiased.  All thirteen planes are
+// rounded this way (the flow populations need it too: rounded to nearest
+// they shift the mean flow of a long run).  The sign is put back before the
+// truncation, which rounds toward zero on either side.  Decoding is
+// binary16's.
 struct CodecF16SR {
   using T = _Float16;
   static constexpr bool dev = true;
   __device__ static __forceinline__ float dec(T v, float off, float one) {
     return __builtin_fmaf((float)v, one, off);
   }
-  __device__ static __forceinline__ T enc(float v, float off, float one, bool) {
+  __device__ static __forceinline__ T enc(float v, float off, float one, uint32_t key) {
     const float x = __builtin_fmaf(v, one, -off);
     const uint32_t xb = __builtin_bit_cast(uint32_t, x);
-    // the lowbias32 mixer of C. Wellons' hash-prospector (its last xorshift
-    // does not reach the top 13 bits, which give r); the first xorshift
-    // carries the high bits of the value into every bit of r
-    uint32_t h = xb ^ (xb >> 16);
-    h *= 0x7feb352du;
-    h ^= h >> 15;
-    h *= 0x846ca68bu;
-    const float r = (float)(h >> 19);
-    // FP32 ulp of |x| (its binade times 2^-23), at least 2^-37
     const uint32_t ab = xb & 0x7fffffffu;
+    const float r = (float)((xb ^ key) >> 19);
+    // FP32 ulp of |x| (its binade times 2^-23), at least 2^-37
     const float ulp = fmaxf(__builtin_bit_cast(float, ab & 0x7f800000u) * 0x1p-23f, 0x1p-37f);
-    const T m = __builtin_amdgcn_cvt_pkrtz(
-        __builtin_fmaf(r, ulp, __builtin_bit_cast(float, ab)), 0.0f)[0];
-    return x < 0.0f ? -m : m;
+    const uint32_t y = __builtin_bit_cast(uint32_t, __builtin_fmaf(r, ulp, __builtin_bit_cast(float, ab)));
+    return __builtin_amdgcn_cvt_pkrtz(__builtin_bit_cast(float, y | (xb & 0x80000000u)), 0.0f)[0];
   }
 };
 struct CodecBF16 {
   using T = __bf16;
   static constexpr bool dev = true;
   __device__ static __forceinline__ float dec(T v, float off, float) { return (float)v + off; }
-  __device__ static __forceinline__ T enc(float v, float off, float, bool) { return (T)(v - off); }
+  __device__ static __forceinline__ T enc(float v, float off, float, uint32_t) {
+    return (T)(v - off);
+  }
 };
 
 template <class C>
@@ -350,9 +372,9 @@ struct Dst {
   gptr<typename C::T> base;
   int64_t plane;
   int32_t pitch;
-  __device__ __forceinline__ void put(const JetDesc &d, int p, int i, int j, float v) const {
-    base[(int64_t)p * plane + node_index(pitch, i, j)] =
-        C::enc(v, pop_offset<C>(d, p), d.one, p >= 9);
+  __device__ __forceinline__ void put(const JetDesc &d, int p, int i, int j, float v,
+                                     uint32_t k) const {
+    base[(int64_t)p * plane + node_index(pitch, i, j)] = C::enc(v, pop_offset<C>(d, p), d.one, k);
   }
 };
 
@@ -462,8 +484,9 @@ struct State {
   __device__ __forceinline__ float load(const JetDesc &d, int p, int i, int j) const {
     return C::dec(*at(p, i, j), pop_offset<C>(d, p), d.one);
   }
-  __device__ __forceinline__ void put(const JetDesc &d, int p, int i, int j, float v) const {
-    *at(p, i, j) = C::enc(v, pop_offset<C>(d, p), d.one, p >= 9);
+  __device__ __forceinline__ void put(const JetDesc &d, int p, int i, int j, float v,
+                                     uint32_t k) const {
+    *at(p, i, j) = C::enc(v, pop_offset<C>(d, p), d.one, k);
   }
   __device__ __forceinline__ float pulled(const JetDesc &d, int p, int i, int j) const {
     const gptr<T> q = kind == 2 ? base + ((int64_t)p * plane + node_index(pitch, i, j))
@@ -537,103 +560,105 @@ __device__ __forceinline__ float4 inlet_at(const float4 *in, int j) {
 template <class C, class O>
 __device__ __forceinline__ void ghost_epilogue(const JetDesc &d, const O &o, int i, int j,
                                                const float (&f)[9], const float (&g)[4],
-                                               const float4 *in) {
+                                               const float4 *in, uint32_t key) {
+  // a copy of population k takes k's key; a computed value its own plane's
+  const auto K = [&](int k) { return plane_key(key, k); };
   const int nx = d.nx, nr = d.nr;
   const int x0 = d.bc[0], x1 = d.bc[1], r0 = d.bc[2], r1 = d.bc[3];
   const bool mir0 = (r0 == BC_AXIS) | (r0 == BC_FREESLIP);
   const bool mir1 = r1 == BC_FREESLIP;
   if (j == 0) {  // ghost row -1: links 2, 5, 6 and g1 (+r)
     if (mir0) {
-      o.put(d, 2, i, -1, f[4]);
-      o.put(d, 5, i, -1, f[8]);
-      o.put(d, 6, i, -1, f[7]);
-      o.put(d, 10, i, -1, g[3]);
+      o.put(d, 2, i, -1, f[4], K(4));
+      o.put(d, 5, i, -1, f[8], K(8));
+      o.put(d, 6, i, -1, f[7], K(7));
+      o.put(d, 10, i, -1, g[3], K(12));
     } else if (r0 == BC_WALL) {
-      o.put(d, 2, i, -1, f[4]);
-      o.put(d, 5, i - 1, -1, f[7]);
-      o.put(d, 6, i + 1, -1, f[8]);
-      o.put(d, 10, i, -1, wall_g(d, 2, g[3]));
+      o.put(d, 2, i, -1, f[4], K(4));
+      o.put(d, 5, i - 1, -1, f[7], K(7));
+      o.put(d, 6, i + 1, -1, f[8], K(8));
+      o.put(d, 10, i, -1, wall_g(d, 2, g[3]), K(10));
     }
   }
   if (j == nr - 1) {  // ghost row nr: links 4, 7, 8 and g3 (-r)
     if (mir1) {
-      o.put(d, 4, i, nr, f[2]);
-      o.put(d, 7, i, nr, f[6]);
-      o.put(d, 8, i, nr, f[5]);
-      o.put(d, 12, i, nr, g[1]);
+      o.put(d, 4, i, nr, f[2], K(2));
+      o.put(d, 7, i, nr, f[6], K(6));
+      o.put(d, 8, i, nr, f[5], K(5));
+      o.put(d, 12, i, nr, g[1], K(10));
     } else if (r1 == BC_WALL) {
-      o.put(d, 4, i, nr, f[2]);
-      o.put(d, 7, i + 1, nr, f[5]);
-      o.put(d, 8, i - 1, nr, f[6]);
-      o.put(d, 12, i, nr, wall_g(d, 3, g[1]));
+      o.put(d, 4, i, nr, f[2], K(2));
+      o.put(d, 7, i + 1, nr, f[5], K(5));
+      o.put(d, 8, i - 1, nr, f[6], K(6));
+      o.put(d, 12, i, nr, wall_g(d, 3, g[1]), K(12));
     }
   }
   if (i == 0) {  // ghost column -1 (rows 0..nr-1): links 1, 5, 8 and g0 (+x)
     if (x0 == BC_INLET) {
       const float4 q = inlet_at(in, j);
-      o.put(d, 1, -1, j, feq_link(1, 1.0f, q.x, q.y));
-      o.put(d, 5, -1, j, feq_link(5, 1.0f, q.x, q.y));
-      o.put(d, 8, -1, j, feq_link(8, 1.0f, q.x, q.y));
-      o.put(d, 9, -1, j, geq_link(0, q.z, q.x, q.y));
+      o.put(d, 1, -1, j, feq_link(1, 1.0f, q.x, q.y), K(1));
+      o.put(d, 5, -1, j, feq_link(5, 1.0f, q.x, q.y), K(5));
+      o.put(d, 8, -1, j, feq_link(8, 1.0f, q.x, q.y), K(8));
+      o.put(d, 9, -1, j, geq_link(0, q.z, q.x, q.y), K(9));
     } else if (x0 == BC_WALL) {
-      o.put(d, 1, -1, j, f[3]);
-      if (j >= 1) o.put(d, 5, -1, j - 1, f[7]);
-      if (j + 1 < nr) o.put(d, 8, -1, j + 1, f[6]);
-      o.put(d, 9, -1, j, wall_g(d, 0, g[2]));
+      o.put(d, 1, -1, j, f[3], K(3));
+      if (j >= 1) o.put(d, 5, -1, j - 1, f[7], K(7));
+      if (j + 1 < nr) o.put(d, 8, -1, j + 1, f[6], K(6));
+      o.put(d, 9, -1, j, wall_g(d, 0, g[2]), K(9));
     }
     if (x1 == BC_PERIODIC) {  // column nx repeats column 0
-      o.put(d, 3, nx, j, f[3]);
-      o.put(d, 6, nx, j, f[6]);
-      o.put(d, 7, nx, j, f[7]);
-      o.put(d, 11, nx, j, g[2]);
+      o.put(d, 3, nx, j, f[3], K(3));
+      o.put(d, 6, nx, j, f[6], K(6));
+      o.put(d, 7, nx, j, f[7], K(7));
+      o.put(d, 11, nx, j, g[2], K(11));
     }
   }
   if (i == nx - 1) {  // ghost column nx: links 3, 6, 7 and g2 (-x)
     if (x1 == BC_OUTFLOW) {
-      o.put(d, 3, nx, j, f[3]);
-      o.put(d, 6, nx, j, f[6]);
-      o.put(d, 7, nx, j, f[7]);
-      o.put(d, 11, nx, j, g[2]);
+      o.put(d, 3, nx, j, f[3], K(3));
+      o.put(d, 6, nx, j, f[6], K(6));
+      o.put(d, 7, nx, j, f[7], K(7));
+      o.put(d, 11, nx, j, g[2], K(11));
     } else if (x1 == BC_WALL) {
-      o.put(d, 3, nx, j, f[1]);
-      if (j >= 1) o.put(d, 6, nx, j - 1, f[8]);
-      if (j + 1 < nr) o.put(d, 7, nx, j + 1, f[5]);
-      o.put(d, 11, nx, j, wall_g(d, 1, g[0]));
+      o.put(d, 3, nx, j, f[1], K(1));
+      if (j >= 1) o.put(d, 6, nx, j - 1, f[8], K(8));
+      if (j + 1 < nr) o.put(d, 7, nx, j + 1, f[5], K(5));
+      o.put(d, 11, nx, j, wall_g(d, 1, g[0]), K(11));
     }
     if (x0 == BC_PERIODIC) {  // column -1 repeats column nx-1
-      o.put(d, 1, -1, j, f[1]);
-      o.put(d, 5, -1, j, f[5]);
-      o.put(d, 8, -1, j, f[8]);
-      o.put(d, 9, -1, j, g[0]);
+      o.put(d, 1, -1, j, f[1], K(1));
+      o.put(d, 5, -1, j, f[5], K(5));
+      o.put(d, 8, -1, j, f[8], K(8));
+      o.put(d, 9, -1, j, g[0], K(9));
     }
   }
   // corner ghosts under a mirror edge: the mirrored link goes through the
   // x rule at the edge row
   if (j == 0 && mir0) {
     // (-1, -1) link 5 <- x rule of link 8 at column -1, row 0
-    if (i == nx - 1 && x0 == BC_PERIODIC) o.put(d, 5, -1, -1, f[8]);
+    if (i == nx - 1 && x0 == BC_PERIODIC) o.put(d, 5, -1, -1, f[8], K(8));
     if (i == 0 && x0 == BC_INLET) {
       const float4 q = inlet_at(in, 0);
-      o.put(d, 5, -1, -1, feq_link(8, 1.0f, q.x, q.y));
+      o.put(d, 5, -1, -1, feq_link(8, 1.0f, q.x, q.y), K(5));
     }
-    if (i == 0 && x0 == BC_WALL) o.put(d, 5, -1, -1, f[6]);
+    if (i == 0 && x0 == BC_WALL) o.put(d, 5, -1, -1, f[6], K(6));
     // (nx, -1) link 6 <- x rule of link 7 at column nx, row 0
-    if (i == 0 && x1 == BC_PERIODIC) o.put(d, 6, nx, -1, f[7]);
-    if (i == nx - 1 && x1 == BC_OUTFLOW) o.put(d, 6, nx, -1, f[7]);
-    if (i == nx - 1 && x1 == BC_WALL) o.put(d, 6, nx, -1, f[5]);
+    if (i == 0 && x1 == BC_PERIODIC) o.put(d, 6, nx, -1, f[7], K(7));
+    if (i == nx - 1 && x1 == BC_OUTFLOW) o.put(d, 6, nx, -1, f[7], K(7));
+    if (i == nx - 1 && x1 == BC_WALL) o.put(d, 6, nx, -1, f[5], K(5));
   }
   if (j == nr - 1 && mir1) {
     // (-1, nr) link 8 <- x rule of link 5 at column -1, row nr-1
-    if (i == nx - 1 && x0 == BC_PERIODIC) o.put(d, 8, -1, nr, f[5]);
+    if (i == nx - 1 && x0 == BC_PERIODIC) o.put(d, 8, -1, nr, f[5], K(5));
     if (i == 0 && x0 == BC_INLET) {
       const float4 q = inlet_at(in, nr - 1);
-      o.put(d, 8, -1, nr, feq_link(5, 1.0f, q.x, q.y));
+      o.put(d, 8, -1, nr, feq_link(5, 1.0f, q.x, q.y), K(8));
     }
-    if (i == 0 && x0 == BC_WALL) o.put(d, 8, -1, nr, f[7]);
+    if (i == 0 && x0 == BC_WALL) o.put(d, 8, -1, nr, f[7], K(7));
     // (nx, nr) link 7 <- x rule of link 6 at column nx, row nr-1
-    if (i == 0 && x1 == BC_PERIODIC) o.put(d, 7, nx, nr, f[6]);
-    if (i == nx - 1 && x1 == BC_OUTFLOW) o.put(d, 7, nx, nr, f[6]);
-    if (i == nx - 1 && x1 == BC_WALL) o.put(d, 7, nx, nr, f[8]);
+    if (i == 0 && x1 == BC_PERIODIC) o.put(d, 7, nx, nr, f[6], K(6));
+    if (i == nx - 1 && x1 == BC_OUTFLOW) o.put(d, 7, nx, nr, f[6], K(6));
+    if (i == nx - 1 && x1 == BC_WALL) o.put(d, 7, nx, nr, f[8], K(8));
   }
 }
 
@@ -644,15 +669,15 @@ __device__ __forceinline__ void ghost_epilogue(const JetDesc &d, const O &o, int
 template <class C>
 __device__ __forceinline__ void aa_epilogue(const JetDesc &d, const State<C> &o, int i, int j,
                                             const float (&f)[9], const float (&g)[4],
-                                            const float4 *in) {
-  ghost_epilogue<C>(d, o, i, j, f, g, in);
+                                            const float4 *in, uint32_t key) {
+  ghost_epilogue<C>(d, o, i, j, f, g, in, key);
   if ((d.bc[0] == BC_EQ) | (d.bc[1] == BC_EQ) | (d.bc[2] == BC_EQ) | (d.bc[3] == BC_EQ)) {
 #pragma unroll
     for (int p = 1; p < NPOP; ++p) {
       const int gi = i - pex(p), gj = j - per(p);
       float v;
       if ((gi < 0 || gi >= d.nx || gj < 0 || gj >= d.nr) && eq_pull(d, p, i, j, v))
-        o.put(d, p, gi, gj, v);
+        o.put(d, p, gi, gj, v, plane_key(sr_key(gi, gj, 0), p));  // as ghost_fill_kernel
     }
   }
 }

@@ -151,6 +151,9 @@ __global__ __launch_bounds__(BX *BY) __attribute__((amdgpu_waves_per_eu(W, 8))) 
         const bool okn = collide(d, rinv, r2, f[e], g[e]);
         ok &= okn | (i0 + e >= d.nx);
       }
+      uint32_t key[NX];
+#pragma unroll
+      for (int e = 0; e < NX; ++e) key[e] = sr_key(i0 + e, j, step + 1);
       if (i0 + NX <= d.nx) {
 #pragma unroll
         for (int p = 0; p < NPOP; ++p) {
@@ -158,7 +161,7 @@ __global__ __launch_bounds__(BX *BY) __attribute__((amdgpu_waves_per_eu(W, 8))) 
           VT v;
 #pragma unroll
           for (int e = 0; e < NX; ++e) {
-            const T x = C::enc(p < 9 ? f[e][p] : g[e][p - 9], off, d.one, p >= 9);
+            const T x = C::enc(p < 9 ? f[e][p] : g[e][p - 9], off, d.one, plane_key(key[e], p));
             if constexpr (NX == 1) v = x; else v[e] = x;
           }
           buf_store<VB, (CP & 1) ? CACHE_NT : 0>(__builtin_bit_cast(typename Raw<VB>::type, v), rd,
@@ -171,8 +174,9 @@ __global__ __launch_bounds__(BX *BY) __attribute__((amdgpu_waves_per_eu(W, 8))) 
           if (i0 + e < d.nx)
 #pragma unroll
             for (int p = 0; p < NPOP; ++p)
-              o[(int64_t)p * d.plane + e] =
-                  C::enc(p < 9 ? f[e][p] : g[e][p - 9], pop_offset<C>(d, p), d.one, p >= 9);
+              o[(int64_t)p * d.plane + e] = C::enc(p < 9 ? f[e][p] : g[e][p - 9],
+                                                   pop_offset<C>(d, p), d.one,
+                                                   plane_key(key[e], p));
       }
       if (tile_edge) {
         const Dst<C> o{as_global(dst_raw), d.plane, d.pitch};
@@ -183,7 +187,7 @@ __global__ __launch_bounds__(BX *BY) __attribute__((amdgpu_waves_per_eu(W, 8))) 
         for (int e = 0; e < NX; ++e) {
           const int i = i0 + e;
           if (i < d.nx && ((i == 0) | (i == d.nx - 1) | (j == 0) | (j == d.nr - 1)))
-            ghost_epilogue<C>(d, o, i, j, f[e], g[e], in_next);
+            ghost_epilogue<C>(d, o, i, j, f[e], g[e], in_next, key[e]);
         }
       }
     }
@@ -235,12 +239,12 @@ __device__ __forceinline__ void load_pulled(const JetDesc &d, __amdgpu_buffer_rs
 template <class C, int AUX>
 __device__ __forceinline__ void store_node(const JetDesc &d, __amdgpu_buffer_rsrc_t rd,
                                            uint32_t voff, uint32_t plane_b, const float (&f)[9],
-                                           const float (&g)[4]) {
+                                           const float (&g)[4], uint32_t key) {
   using T = typename C::T;
   constexpr int ES = (int)sizeof(T);
 #pragma unroll
   for (int p = 0; p < NPOP; ++p) {
-    const T x = C::enc(p < 9 ? f[p] : g[p - 9], pop_offset<C>(d, p), d.one, p >= 9);
+    const T x = C::enc(p < 9 ? f[p] : g[p - 9], pop_offset<C>(d, p), d.one, plane_key(key, p));
     buf_store<ES, AUX>(__builtin_bit_cast(typename Raw<ES>::type, x), rd, voff,
                        (uint32_t)p * plane_b);
   }
@@ -260,9 +264,9 @@ constexpr int PAIR_W = 66;
 // Planes below P0 are not kept (P0 = 1: the rest population stays in the
 // registers of the thread that computed it, see pair_kernel).
 template <class C>
-__device__ __forceinline__ float storage_round(const JetDesc &d, int p, float v) {
+__device__ __forceinline__ float storage_round(const JetDesc &d, int p, float v, uint32_t k) {
   const float off = pop_offset<C>(d, p);
-  return C::dec(C::enc(v, off, d.one, p >= 9), off, d.one);
+  return C::dec(C::enc(v, off, d.one, k), off, d.one);
 }
 
 template <class C, int EH, int P0>
@@ -270,14 +274,16 @@ struct LdsImage {
   float *s;
   int ia, ja;
   int wrap;  // nx for periodic x edges (a column nx away is the same column), else 0
-  __device__ __forceinline__ void set(const JetDesc &d, int p, int x, int y, float v) const {
-    if (p >= P0) s[((p - P0) * EH + y) * PAIR_W + x] = storage_round<C>(d, p, v);
+  __device__ __forceinline__ void set(const JetDesc &d, int p, int x, int y, float v,
+                                     uint32_t k) const {
+    if (p >= P0) s[((p - P0) * EH + y) * PAIR_W + x] = storage_round<C>(d, p, v, k);
   }
-  __device__ __forceinline__ void put(const JetDesc &d, int p, int i, int j, float v) const {
+  __device__ __forceinline__ void put(const JetDesc &d, int p, int i, int j, float v,
+                                     uint32_t k) const {
     int x = i - ia + 1;
     const int y = j - ja + 1;
     if (wrap) x += x < 0 ? wrap : (x >= PAIR_W ? -wrap : 0);
-    if (((unsigned)x < (unsigned)PAIR_W) & ((unsigned)y < (unsigned)EH)) set(d, p, x, y, v);
+    if (((unsigned)x < (unsigned)PAIR_W) & ((unsigned)y < (unsigned)EH)) set(d, p, x, y, v, k);
   }
 };
 
@@ -364,8 +370,9 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(W, 8)))
           load_pulled<C, AUX_L>(d, rs, voff, plane_b, pitch_b, f, g);
           const float rr = d.r0 + (float)j + 0.5f;
           ok &= collide(d, fast_rcp(rr), rr * rr, f, g);
-          store_node<C, AUX_S>(d, rd, voff, plane_b, f, g);
-          if (is_edge(d, i, j)) ghost_epilogue<C>(d, out, i, j, f, g, in1);
+          const uint32_t key = sr_key(i, j, step + 1);
+          store_node<C, AUX_S>(d, rd, voff, plane_b, f, g, key);
+          if (is_edge(d, i, j)) ghost_epilogue<C>(d, out, i, j, f, g, in1, key);
         }
       }
     } else {
@@ -450,13 +457,15 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(W, 8)))
           bool okn;
           if constexpr (PF) okn = collide(d, fast_rcp(rr), rr * rr, f, g, prefetch);
           else okn = collide(d, fast_rcp(rr), rr * rr, f, g);
+          const uint32_t key = sr_key(i, j, step + 1);
           if ((y < EH) & (i >= 0) & (i < nx) & (j >= 0) & (j < nr)) {
             ok &= okn;
 #pragma unroll
-            for (int p = 0; p < NPOP; ++p) im.set(d, p, x, y, p < 9 ? f[p] : g[p - 9]);
-            if (is_edge(d, i, j)) ghost_epilogue<C>(d, im, i, j, f, g, in1);
+            for (int p = 0; p < NPOP; ++p)
+              im.set(d, p, x, y, p < 9 ? f[p] : g[p - 9], plane_key(key, p));
+            if (is_edge(d, i, j)) ghost_epilogue<C>(d, im, i, j, f, g, in1, key);
           }
-          if (P0 == 1) keep0[k] = storage_round<C>(d, 0, f[0]);
+          if (P0 == 1) keep0[k] = storage_round<C>(d, 0, f[0], plane_key(key, 0));
         }
       }
       __syncthreads();
@@ -474,8 +483,9 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(W, 8)))
           const float rr = d.r0 + (float)j + 0.5f;
           ok &= collide(d, fast_rcp(rr), rr * rr, f, g);
           const uint32_t voff = (uint32_t)node_index(d.pitch, i, j) * ES;
-          store_node<C, AUX_S>(d, rd, voff, plane_b, f, g);
-          if (tile_edge && is_edge(d, i, j)) ghost_epilogue<C>(d, out, i, j, f, g, in2);
+          const uint32_t key = sr_key(i, j, step + 2);
+          store_node<C, AUX_S>(d, rd, voff, plane_b, f, g, key);
+          if (tile_edge && is_edge(d, i, j)) ghost_epilogue<C>(d, out, i, j, f, g, in2, key);
         }
       };
       if constexpr (P0 == 1) {
@@ -556,9 +566,10 @@ __global__ __launch_bounds__(256) void aa_kernel(
       decode_raw<C>(d, w, f, g);
       const float rr = d.r0 + (float)j + 0.5f;
       const bool ok = collide(d, fast_rcp(rr), rr * rr, f, g);
+      const uint32_t key = sr_key(i, j, step + 1);
 #pragma unroll
       for (int p = 0; p < NPOP; ++p) {
-        const T x = C::enc(p < 9 ? f[p] : g[p - 9], pop_offset<C>(d, p), d.one, p >= 9);
+        const T x = C::enc(p < 9 ? f[p] : g[p - 9], pop_offset<C>(d, p), d.one, plane_key(key, p));
         const uint32_t soff =
             swapped ? (uint32_t)p * plane_b + (uint32_t)(per(p) * (int)pitch_b) +
                           (uint32_t)(pex(p) * ES)
@@ -570,7 +581,7 @@ __global__ __launch_bounds__(256) void aa_kernel(
                                 ? d.inlet + (int64_t)((step + 1) % d.n_t) * d.nr
                                 : d.inlet;
         const State<C> o{as_global(raw), d.plane, d.pitch, swapped ? 2 : 1};
-        aa_epilogue<C>(d, o, i, j, f, g, in1);
+        aa_epilogue<C>(d, o, i, j, f, g, in1, key);
       }
       if (!ok) flags[d.slot] = 1;
     }
@@ -581,7 +592,10 @@ __global__ __launch_bounds__(256) void aa_kernel(
 // interior and the inlet row of `step`, by the pull-side edge rules: every
 // ghost slot (ghost node, link p) whose puller (ghost + e_p) is a fluid node
 // gets the value that node pulls.  Run after any change of the interior or
-// of the inlet made outside the step.
+// of the inlet made outside the step.  The rounding key is the ghost
+// position's at step 0, whatever the step: the constant ghosts of
+// equilibrium sides then hold the same bits in both buffers, which the
+// single-buffer kernel rewrites with the same key every step.
 // One thread per ghost node: row -1 and row nr (nx + 2 each, corners
 // included), then columns -1 and nx (nr each).
 template <class C>
@@ -601,7 +615,8 @@ __global__ void ghost_fill_kernel(const JetDesc *__restrict__ dp, int64_t step, 
   for (int p = 1; p < NPOP; ++p) {
     const int pi = gi + pex(p), pj = gj + per(p);
     if (pi >= 0 && pi < nx && pj >= 0 && pj < nr)
-      st.put(d, p, gi, gj, pull_edge<C>(d, st, p, pi, pj, inrow));
+      st.put(d, p, gi, gj, pull_edge<C>(d, st, p, pi, pj, inrow),
+             plane_key(sr_key(gi, gj, 0), p));
   }
 }
 
@@ -633,8 +648,10 @@ __global__ void init_kernel(const JetDesc *__restrict__ dp, int64_t step, int32_
   if (i >= d.nx) return;
   const float4 q = state ? state[(int64_t)j * d.nx + i] : u0;
   const State<C> st = state_view<C>(d, view);
+  const uint32_t key = sr_key(i, j, step);
 #pragma unroll
-  for (int p = 0; p < NPOP; ++p) st.put(d, p, i, j, eq_plane(p, q.x, q.y, q.z, q.w));
+  for (int p = 0; p < NPOP; ++p)
+    st.put(d, p, i, j, eq_plane(p, q.x, q.y, q.z, q.w), plane_key(key, p));
 }
 
 // Pre-collision moments (eq. 2) of the state after `step` steps:
@@ -753,7 +770,8 @@ __global__ void encode_kernel(const JetDesc *__restrict__ dp, int64_t step, int3
   const JetDesc &d = *dp;
   const int i = blockIdx.x * blockDim.x + threadIdx.x, j = blockIdx.y, p = blockIdx.z;
   if (i >= d.nx) return;
-  state_view<C>(d, view).put(d, p, i, j, in[((int64_t)p * d.nr + j) * d.nx + i]);
+  state_view<C>(d, view).put(d, p, i, j, in[((int64_t)p * d.nr + j) * d.nx + i],
+                            plane_key(sr_key(i, j, step), p));
 }
 
 // Plain streaming copy, 16 B per lane per iteration.

@@ -10,8 +10,10 @@ directly.  Properties checked:
   subnormal, both signs);
 * the number of values rounded up matches the sum of their discarded
   fractions within 5 standard deviations of that binomial sum (unbiased);
-* the same value rounds the same way wherever it is stored, and writing the
-  same data again gives the same bits (reproducible).
+* the rounding key is the node's and the step's: one value stored at every
+  node rounds up at a share of them equal to its discarded fraction, writing
+  the same data for the same step gives the same bits, and writing it for
+  another step draws new keys (reproducible, and independent over steps).
 """
 import numpy as np
 import pytest
@@ -37,10 +39,10 @@ def solver():
         yield s
 
 
-def _round_trip(s, g_values):
+def _round_trip(s, g_values, step=0):
     w = np.array([4 / 9] + [1 / 9] * 4 + [1 / 36] * 4)
     f = np.broadcast_to(w[:, None, None], (9, NR, NX)).copy()
-    s.set_populations(f, np.asarray(g_values, np.float64).reshape(4, NR, NX), 0)
+    s.set_populations(f, np.asarray(g_values, np.float64).reshape(4, NR, NX), step)
     return s.get_populations()[1].reshape(-1)
 
 
@@ -99,10 +101,32 @@ def test_fixed_fraction(solver, phi):
     assert abs(up.mean() - phi) < 5 * sd
 
 
+@pytest.mark.parametrize("phi", [0.125, 0.5, 0.8125])
+def test_one_value_everywhere(solver, phi):
+    """One value at every node of the four planes: the share rounded up is
+    its discarded fraction (the keys of 65 536 positions)."""
+    v = (1024 + 301 + phi) * 2.0 ** -16  # a normal binary16 spacing of 2^-16
+    got = _round_trip(solver, np.full(N, v))
+    lo, hi = (1024 + 301) * 2.0 ** -16, (1024 + 302) * 2.0 ** -16
+    assert np.all((got == lo) | (got == hi))
+    up = float(np.mean(got == hi))
+    sd = np.sqrt(phi * (1 - phi) / N)
+    print(f"phi {phi}: {up:.4f} up of {N} (sd {sd:.4f})")
+    assert abs(up - phi) < 5 * sd
+
+
 def test_reproducible(solver):
     rng = np.random.default_rng(13)
-    base = (rng.uniform(-0.3, 0.3, N // 8)).astype(np.float32).astype(np.float64)
-    v = np.tile(base, 8)  # each value at eight places, in every plane
-    a = _round_trip(solver, v)
-    assert np.array_equal(a.reshape(8, -1), np.broadcast_to(a[: N // 8], (8, N // 8)))
-    assert np.array_equal(_round_trip(solver, v), a)
+    v = rng.uniform(-0.3, 0.3, N).astype(np.float32).astype(np.float64)
+    a = _round_trip(solver, v, step=5)
+    assert np.array_equal(_round_trip(solver, v, step=5), a)
+    # another step, other keys: about half the values that do not sit on a
+    # binary16 number round the other way (independent draws)
+    b = _round_trip(solver, v, step=6)
+    lo, hi = _neighbours(v)
+    inexact = lo != v
+    phi = (np.abs(v) - np.abs(lo)) / (np.abs(hi) - np.abs(lo))
+    expect = float(np.sum((2 * phi * (1 - phi))[inexact]))
+    differ = int(np.sum((a != b)[inexact]))
+    print(f"{differ} of {int(inexact.sum())} differ, expected {expect:.0f}")
+    assert abs(differ - expect) < 5 * np.sqrt(expect)
