@@ -45,10 +45,12 @@ struct lbm_handle {
   Scratch scratch;
   JetDesc desc{};
   int64_t step = 0;  // steps done
-  int64_t base = 0;  // step0 held by the device descriptor
-  int32_t flip = 0;  // state after s steps in buf[(s + flip) & 1]; the device
-                     // descriptor holds the same value (two-step launches are
-                     // always followed by an advance)
+  int32_t flip = 0;  // state after s steps in buf[(s + flip) & 1]
+  // step0 and flip held by the device descriptor: they may lag step and flip
+  // (directly launched steps pass the difference as koff and tog; a graph,
+  // whose arguments are fixed, first brings them up to date)
+  int64_t base = 0;
+  int32_t dflip = 0;
   int shape = 0;
   int32_t ntiles = 0, grid = 0;
   bool unstable = false;
@@ -64,6 +66,8 @@ int32_t view_of(const lbm_handle *h, int64_t step) {
 }
 
 int upload_desc(lbm_handle *h) {
+  h->base = h->step;
+  h->dflip = h->flip;
   h->desc.step0 = h->base;
   h->desc.flip = h->flip;
   LBM_HIP(hipMemcpyAsync(h->d_desc, &h->desc, sizeof(JetDesc), hipMemcpyHostToDevice, h->stream));
@@ -252,20 +256,23 @@ int one_step(lbm_handle *h, int32_t koff, int32_t tog) {
 }
 
 // The launches of a group of k steps on `st`: with a two-step shape, k / 2
-// pair launches (and one single step if k is odd), then the descriptor
-// advance.
-int enqueue_group(lbm_handle *h, int32_t k, bool pair, hipStream_t st) {
+// pair launches (and one single step if k is odd), starting koff0 steps past
+// the descriptor's step0 with its flip toggled by tog0; then, if `advance`,
+// the descriptor advance (koff0 = tog0 = 0 then).
+int enqueue_group(lbm_handle *h, int32_t k, bool pair, hipStream_t st, int32_t koff0 = 0,
+                  int32_t tog0 = 0, bool advance = true) {
   int rc = LBM_OK;
   const int32_t np = pair ? k / 2 : 0;
   for (int32_t q = 0; q < np && !rc; ++q)
-    rc = launch_step(h->shape, h->prec, h->grid, st, h->d_desc, h->d_tiles, h->d_hdr, 2 * q,
-                     q & 1, 2, h->d_flag);
+    rc = launch_step(h->shape, h->prec, h->grid, st, h->d_desc, h->d_tiles, h->d_hdr,
+                     koff0 + 2 * q, tog0 ^ (q & 1), 2, h->d_flag);
   for (int32_t q = 2 * np; q < k && !rc; ++q)
     rc = h->layout == LBM_LAYOUT_SINGLE
-             ? launch_aa_step(h->prec, h->grid, st, h->d_desc, h->d_tiles, h->d_hdr, q, h->d_flag)
-             : launch_step(h->shape, h->prec, h->grid, st, h->d_desc, h->d_tiles, h->d_hdr, q,
-                           np & 1, 1, h->d_flag);
-  if (!rc) rc = launch_advance(st, h->d_desc, h->d_hdr, 1, k, np);
+             ? launch_aa_step(h->prec, h->grid, st, h->d_desc, h->d_tiles, h->d_hdr, koff0 + q,
+                              h->d_flag)
+             : launch_step(h->shape, h->prec, h->grid, st, h->d_desc, h->d_tiles, h->d_hdr,
+                           koff0 + q, tog0 ^ (np & 1), 1, h->d_flag);
+  if (!rc && advance) rc = launch_advance(st, h->d_desc, h->d_hdr, 1, k, np);
   return rc;
 }
 
@@ -302,7 +309,7 @@ int prepare_graph(lbm_handle *h) {
   // first launch: with the descriptor's target at its step0 every tile is
   // skipped and the advance leaves step0 and flip as they are, so the state
   // does not change.
-  h->desc.target = h->base;
+  h->desc.target = h->step;  // (upload_desc sets step0 to the step count)
   int rc2 = upload_desc(h);
   if (!rc2 && hipGraphLaunch(h->gexec, h->stream) != hipSuccess) rc2 = LBM_EDEVICE;
   if (!rc2 && hipStreamSynchronize(h->stream) != hipSuccess) rc2 = LBM_EDEVICE;
@@ -311,18 +318,25 @@ int prepare_graph(lbm_handle *h) {
   return rc2 ? rc2 : rc3;
 }
 
+// Brings the device descriptor's step0 and flip to the host's.
+int catch_up(lbm_handle *h) {
+  if (h->base == h->step && h->dflip == h->flip) return LBM_OK;
+  const int rc = launch_advance(h->stream, h->d_desc, h->d_hdr, 1, (int32_t)(h->step - h->base),
+                                h->flip ^ h->dflip);
+  if (rc) return rc;
+  h->base = h->step;
+  h->dflip = h->flip;
+  return LBM_OK;
+}
+
 int launch_steps(lbm_handle *h, int64_t n) {
   int nsh;
   const bool pair = tile_shapes(&nsh)[h->shape].steps == 2;
   int rc;
   while (n > 0) {
     const bool graph = h->graph_k > 0 && n >= h->graph_k;
-    if (h->base != h->step && (pair || graph || h->step - h->base > (1 << 30))) {
-      // bring the device step0 to the host count (single steps only since)
-      rc = launch_advance(h->stream, h->d_desc, h->d_hdr, 1, (int32_t)(h->step - h->base), 0);
-      if (rc) return rc;
-      h->base = h->step;
-    }
+    // (the lag is kept below 2^30 steps, so koff fits its 32 bits)
+    if ((graph || h->step - h->base > (1 << 30)) && (rc = catch_up(h))) return rc;
     if (graph) {
       if (!h->gexec || h->gexec_k != h->graph_k || h->gexec_shape != h->shape) {
         drop_graph(h);
@@ -331,20 +345,25 @@ int launch_steps(lbm_handle *h, int64_t n) {
       LBM_HIP(hipGraphLaunch(h->gexec, h->stream));
       h->step += h->graph_k;
       h->base += h->graph_k;
-      if (pair) h->flip ^= (h->graph_k / 2) & 1;
+      if (pair) {
+        h->flip ^= (h->graph_k / 2) & 1;
+        h->dflip ^= (h->graph_k / 2) & 1;
+      }
       n -= h->graph_k;
     } else if (pair) {
-      // the rest (fewer steps than a graph holds) as one directly launched
-      // group: the same launches as a graph, one advance at the end, so the
-      // device descriptor (step0, flip) matches the host afterwards
+      // the rest (fewer steps than a graph holds) as directly launched
+      // steps: a graph's launches, offset from the descriptor, and no
+      // advance (the device starts on the first kernel while the host
+      // enqueues the rest)
       const int32_t m = (int32_t)std::min<int64_t>(n, 1 << 20);
-      if ((rc = enqueue_group(h, m, true, h->stream))) return rc;
+      if ((rc = enqueue_group(h, m, true, h->stream, (int32_t)(h->step - h->base),
+                              h->flip ^ h->dflip, false)))
+        return rc;
       h->step += m;
-      h->base += m;
       h->flip ^= (m / 2) & 1;
       n -= m;
     } else {
-      rc = one_step(h, (int32_t)(h->step - h->base), 0);
+      rc = one_step(h, (int32_t)(h->step - h->base), h->flip ^ h->dflip);
       if (rc) return rc;
       h->step += 1;
       n -= 1;

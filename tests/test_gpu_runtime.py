@@ -36,6 +36,45 @@ def test_tile_shapes_and_graphs_bitwise_identical():
         assert np.array_equal(f, f0) and np.array_equal(g, g0), k
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp16sr"])
+def test_step_calls_of_any_length(precision):
+    """Calls of odd and even lengths, shorter and longer than a graph, with
+    reads, an inlet change and a graph-size change in between: directly
+    launched steps leave the device descriptor behind and pass the
+    difference as arguments, graph replays catch it up first; the result is
+    that of one call of one-step launches."""
+    from paper_1002_3028_amd import lbm
+    p = tiny_params(200, 45, "jet", 1)
+    inlet, inlet2 = noisy_inlet(45, 5, 1), noisy_inlet(45, 3, 2)
+    calls = (1, 3, 20, 50, 7, 2, 41, 1, 60, 5)
+    assert lbm.tile_shape_info(0)["steps"] == 1  # the reference: one step per launch
+
+    def ref():
+        with lbm.Solver(p, precision, tile_shape=0) as s:
+            s.set_inlet(*inlet)
+            s.step(sum(calls[:5]))
+            s.set_inlet(*inlet2)
+            s.step(sum(calls[5:]))
+            return s.get_populations()
+
+    f0, g0 = ref()
+    pair = [q for q, inf in enumerate(lbm.tile_shape_infos()) if inf["steps"] == 2][0]
+    with lbm.Solver(p, precision, graph_steps=20, tile_shape=pair) as s:
+        s.set_inlet(*inlet)
+        for q, n in enumerate(calls):
+            if q == 5:
+                s.set_inlet(*inlet2)
+            if q == 7:
+                s.set_graph_steps(16)
+            s.step(n)
+            if q in (2, 6):
+                s.conservation()
+                s.profiles()
+        assert s.step_count == sum(calls)
+        f, g = s.get_populations()
+    assert np.array_equal(f, f0) and np.array_equal(g, g0)
+
+
 def test_deterministic_repeat():
     p = tiny_params(300, 64, "jet", 0)
     inlet = noisy_inlet(64, 3, 2)
