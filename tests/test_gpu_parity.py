@@ -56,6 +56,34 @@ def test_populations_match_oracle(case, nx, nr):
         assert gpu.step_count == ref.step_count == CHECKPOINTS[-1]
 
 
+@pytest.mark.parametrize("case", ["annulus", "jet"])
+def test_tables_clamped_outside_their_range(case):
+    """Eq. (6) tables over T in [0.3, 0.7] while the state's T runs from
+    about 0 to 1 (hot and cold walls, a hot inlet): the lookup takes both
+    clamp branches on the GPU as in the oracle."""
+    from paper_1002_3028_amd import inputs
+    p = dict(tiny_params(70, 17, case, 1), t_lo=0.3, t_hi=0.7)
+    st = inputs.perturbed_state(70, 17, seed=5, amp=0.02, T_mean=0.5, T_amp=0.45)
+    inlet = noisy_inlet(17, 7, seed=3)
+    gpu, ref = _pair(p)
+    with gpu, ref:
+        for s in (gpu, ref):
+            s.set_inlet(*inlet)
+            s.set_state(*st)
+        T = ref.moments()["T"]
+        assert T.min() < 0.3 - 0.1 and T.max() > 0.7 + 0.1, (T.min(), T.max())
+        done = 0
+        for n in CHECKPOINTS:
+            gpu.step(n - done)
+            ref.step(n - done)
+            done = n
+            fg, gg = gpu.get_populations()
+            fr, gr = ref.get_populations()
+            ef, eg = rel_err(fg, fr), rel_err(gg, gr)
+            print(f"{case} clamped tables step {n}: f {ef:.2e} g {eg:.2e}")
+            assert ef < POP_TOL[n] and eg < POP_TOL[n], (case, n, ef, eg)
+
+
 def test_small_jet_500_steps():
     """128 x 32 jet, 500 steps: u and T within 1e-4 of the field scale."""
     from paper_1002_3028_amd import inputs

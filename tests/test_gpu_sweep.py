@@ -45,10 +45,15 @@ def test_umax_sweep_batched():
         assert np.all(c[dev] > a[dev])
     for a, c in zip(T_axis, T_axis[1:]):
         assert np.all(c[dev] >= a[dev])
-    # one jet against the oracle
-    p, inlet, steps = jets[-1]
-    with oracle.RefSolver(p, threads=host_threads()) as r:
-        r.set_inlet(*inlet)
-        r.step(steps)
-        ref = r.profiles()
-    assert rel_err(axis[-1], ref["ux_axis"]) < 1e-3
+    # every jet against the oracle.  After 1 500 steps the FP32 and FP64
+    # trajectories of these unsteady jets have begun to separate in u_x
+    # (the serving jets' FP32 u_x error is 8.5e-4 at 1 000 steps and 2.2e-3
+    # at 2 000); T, the smooth field, is held to 1e-3
+    for q, (p, inlet, steps) in enumerate(jets):
+        with oracle.RefSolver(p, threads=host_threads()) as r:
+            r.set_inlet(*inlet)
+            r.step(steps)
+            ref = r.profiles()
+        eu, eT = rel_err(axis[q], ref["ux_axis"]), rel_err(T_axis[q], ref["T_axis"])
+        print(f"U_max jet {q}: centreline u_x {eu:.2e}, T {eT:.2e}")
+        assert eu < 3e-3 and eT < 1e-3, (q, eu, eT)
