@@ -103,7 +103,6 @@ void fill_desc(JetDesc &d, const lbm_config *c) {
   d.t_scale = c->table_n == 0 ? 0.f : (float)((c->table_n - 1) / (c->t_hi - c->t_lo));
   d.rho_ref = (float)c->rho_ref;
   d.g4_ref = (float)(0.25 * c->g_ref);
-  d.one = 1.0f;
   d.flip = 0;
 }
 

@@ -140,7 +140,7 @@ __global__ __launch_bounds__(BX *BY) __attribute__((amdgpu_waves_per_eu(W, 8))) 
         const float off = pop_offset<C>(d, p);
 #pragma unroll
         for (int e = 0; e < NX; ++e) {
-          const float x = C::dec(elem<T, NX>(v, e), off, d.one);
+          const float x = C::dec(elem<T, NX>(v, e), off);
           if (p < 9) f[e][p] = x; else g[e][p - 9] = x;
         }
       }
@@ -161,7 +161,7 @@ __global__ __launch_bounds__(BX *BY) __attribute__((amdgpu_waves_per_eu(W, 8))) 
           VT v;
 #pragma unroll
           for (int e = 0; e < NX; ++e) {
-            const T x = C::enc(p < 9 ? f[e][p] : g[e][p - 9], off, d.one, plane_key(key[e], p));
+            const T x = C::enc(p < 9 ? f[e][p] : g[e][p - 9], off, plane_key(key[e], p));
             if constexpr (NX == 1) v = x; else v[e] = x;
           }
           buf_store<VB, (CP & 1) ? CACHE_NT : 0>(__builtin_bit_cast(typename Raw<VB>::type, v), rd,
@@ -175,8 +175,7 @@ __global__ __launch_bounds__(BX *BY) __attribute__((amdgpu_waves_per_eu(W, 8))) 
 #pragma unroll
             for (int p = 0; p < NPOP; ++p)
               o[(int64_t)p * d.plane + e] = C::enc(p < 9 ? f[e][p] : g[e][p - 9],
-                                                   pop_offset<C>(d, p), d.one,
-                                                   plane_key(key[e], p));
+                                                   pop_offset<C>(d, p), plane_key(key[e], p));
       }
       if (tile_edge) {
         const Dst<C> o{as_global(dst_raw), d.plane, d.pitch};
@@ -221,7 +220,7 @@ __device__ __forceinline__ void decode_raw(const JetDesc &d,
   using T = typename C::T;
 #pragma unroll
   for (int p = 0; p < NPOP; ++p) {
-    const float x = C::dec(__builtin_bit_cast(T, raw[p]), pop_offset<C>(d, p), d.one);
+    const float x = C::dec(__builtin_bit_cast(T, raw[p]), pop_offset<C>(d, p));
     if (p < 9) f[p] = x; else g[p - 9] = x;
   }
 }
@@ -244,7 +243,7 @@ __device__ __forceinline__ void store_node(const JetDesc &d, __amdgpu_buffer_rsr
   constexpr int ES = (int)sizeof(T);
 #pragma unroll
   for (int p = 0; p < NPOP; ++p) {
-    const T x = C::enc(p < 9 ? f[p] : g[p - 9], pop_offset<C>(d, p), d.one, plane_key(key, p));
+    const T x = C::enc(p < 9 ? f[p] : g[p - 9], pop_offset<C>(d, p), plane_key(key, p));
     buf_store<ES, AUX>(__builtin_bit_cast(typename Raw<ES>::type, x), rd, voff,
                        (uint32_t)p * plane_b);
   }
@@ -266,7 +265,7 @@ constexpr int PAIR_W = 66;
 template <class C>
 __device__ __forceinline__ float storage_round(const JetDesc &d, int p, float v, uint32_t k) {
   const float off = pop_offset<C>(d, p);
-  return C::dec(C::enc(v, off, d.one, k), off, d.one);
+  return C::dec(C::enc(v, off, k), off);
 }
 
 template <class C, int EH, int P0>
@@ -569,7 +568,7 @@ __global__ __launch_bounds__(256) void aa_kernel(
       const uint32_t key = sr_key(i, j, step + 1);
 #pragma unroll
       for (int p = 0; p < NPOP; ++p) {
-        const T x = C::enc(p < 9 ? f[p] : g[p - 9], pop_offset<C>(d, p), d.one, plane_key(key, p));
+        const T x = C::enc(p < 9 ? f[p] : g[p - 9], pop_offset<C>(d, p), plane_key(key, p));
         const uint32_t soff =
             swapped ? (uint32_t)p * plane_b + (uint32_t)(per(p) * (int)pitch_b) +
                           (uint32_t)(pex(p) * ES)
