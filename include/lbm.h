@@ -240,8 +240,9 @@ int lbm_probe_copy(void *dst, const void *src, size_t bytes, void *hip_stream);
  * steps of one persistent launch per step over all its jets (HIP graphs),
  * cohorts alternating between two streams (lbm_batch_set_streams).  A jet
  * stops at its own target step count.  Each jet's result is bitwise the
- * same as that of the same jet run alone.  Precision is common to the
- * batch. */
+ * same as that of the same jet run alone.  `precision` is the batch's
+ * storage form; a jet admitted with another (cfg->precision) joins cohorts
+ * of its own form, so one batch serves jets of several storage forms. */
 typedef struct lbm_batch lbm_batch;
 int lbm_batch_create(size_t budget_bytes, int32_t max_slots, int32_t precision,
                      void *hip_stream, lbm_batch **out);
@@ -250,9 +251,10 @@ int lbm_batch_create(size_t budget_bytes, int32_t max_slots, int32_t precision,
  * LBM_LAYOUT_SINGLE a jet takes half the budget and every launch advances
  * one step. */
 int lbm_batch_set_layout(lbm_batch *b, int32_t layout);
-/* Admit a jet (cfg->precision and cfg->layout are ignored).  LBM_ENOMEM when
- * the budget or the slot table is full.  n_t/ux/ur/T as lbm_set_inlet (n_t = 0:
- * ambient). */
+/* Admit a jet.  cfg->precision is the jet's storage form (LBM_PREC_FP32,
+ * _FP16DEV, _BF16DEV or _FP16SR; 0 = the batch's; others LBM_EINVAL);
+ * cfg->layout is ignored (the batch's).  LBM_ENOMEM when the budget or the
+ * slot table is full.  n_t/ux/ur/T as lbm_set_inlet (n_t = 0: ambient). */
 int lbm_batch_admit(lbm_batch *b, const lbm_config *cfg, int32_t n_t,
                     const double *ux, const double *ur, const double *T,
                     int64_t target_steps, int32_t *slot);
@@ -281,12 +283,14 @@ int lbm_batch_moments(lbm_batch *b, int32_t slot, double *rho, double *ux,
 int lbm_batch_retire(lbm_batch *b, int32_t slot);
 /* Wait for the batch's queued work; LBM_EDEVICE on an asynchronous error. */
 int lbm_batch_sync(lbm_batch *b);
-/* Bytes a jet of this configuration takes from the budget. */
+/* Bytes a jet of this configuration (and storage form, as for
+ * lbm_batch_admit) takes from the budget. */
 int lbm_batch_jet_bytes(const lbm_batch *b, const lbm_config *cfg, size_t *bytes);
 int lbm_batch_active(const lbm_batch *b, int32_t *n_active, size_t *bytes_used);
-/* Tile shape of the step kernel (index into the compiled shapes; -1 = auto)
- * and the number of persistent workgroups (0 = auto: as many as the device
- * holds at once for that kernel). */
+/* Tile shape of the step kernel (index into the compiled shapes; -1 = auto,
+ * the default shape of each storage form) and the number of persistent
+ * workgroups (0 = auto: as many as the device holds at once for that
+ * kernel); both apply to every storage form of the batch. */
 int lbm_batch_set_launch(lbm_batch *b, int32_t tile_shape, int32_t workgroups);
 /* Cohort size limit in bytes of population buffers (0: all jets together;
  * default 128 MiB, so that the two cohorts running at once fill the 256 MiB

@@ -9,6 +9,11 @@
 // jets, so the captured graph of k steps of a cohort is replayed as jets come
 // and go.
 //
+// A batch holds jets of several storage forms (the batch's own unless a
+// jet's configuration names another); each cohort holds one form, so that
+// a serving loop can route some requests to another form without a second
+// batch, whose groups would double the launches per group.
+//
 // Runs only enqueue, so that a serving loop can queue the next group before
 // it retires and admits jets: the cohort lists exist twice (a rebuild writes
 // the copy that the groups in flight do not read), every group records an
@@ -29,6 +34,8 @@ namespace {
 
 struct Slot {
   bool used = false;
+  int prec = LBM_PREC_FP32;  // the jet's storage form
+  int shape = 0;             // tile shape of its cohort (set by rebuild)
   lbm_config cfg{};
   std::vector<double> nu_tab, al_tab;
   JetDesc desc{};
@@ -134,10 +141,16 @@ struct lbm_batch {
   std::vector<int32_t> active;  // slots in the compact list, in order
   bool dirty = true;
   int shape = -1;       // -1: auto
-  int cur_shape = 0;    // shape of the current cohorts (set by rebuild)
   int32_t wg = 0;       // 0: auto
-  int32_t grid = 0;
-  std::map<std::tuple<int, int, int, int, int>, hipGraphExec_t> graphs;  // (k, shape, grid, cohort, copy)
+  // storage form, tile shape and grid of each cohort of each copy of the
+  // lists (set by rebuild)
+  struct Cohort {
+    int prec = LBM_PREC_FP32, shape = 0;
+    int32_t grid = 0;
+  };
+  std::vector<Cohort> cohorts[2];
+  // (k, shape, grid, cohort, copy, storage form)
+  std::map<std::tuple<int, int, int, int, int, int>, hipGraphExec_t> graphs;
   // cohorts alternate between the batch's stream and a second one, so that
   // one cohort's launches fill the device while the other's start or drain
   static constexpr int MAX_STREAMS = 4;
@@ -149,10 +162,20 @@ struct lbm_batch {
 
 namespace {
 
-// The requested (or default) shape.
-int pick_shape(const lbm_batch *b) {
+// The requested (or default) shape for a storage form.
+int pick_shape(const lbm_batch *b, int prec) {
   if (b->layout == LBM_LAYOUT_SINGLE) return 0;  // the in-place kernel's tiles
-  return b->shape >= 0 ? b->shape : default_tile_shape(b->prec);
+  return b->shape >= 0 ? b->shape : default_tile_shape(prec);
+}
+
+bool storage_form(int prec) {
+  return prec == LBM_PREC_FP32 || prec == LBM_PREC_FP16DEV || prec == LBM_PREC_BF16DEV ||
+         prec == LBM_PREC_FP16SR;
+}
+
+// A jet's storage form: its configuration's, or the batch's for 0.
+int jet_prec(const lbm_batch *b, const lbm_config *cfg) {
+  return cfg->precision == 0 ? b->prec : cfg->precision;
 }
 
 void drop_graphs(lbm_batch *b) {
@@ -173,25 +196,53 @@ Lists lists_of(const lbm_batch *b, int32_t cp) {
           b->d_hdr + cp * mc, b->h_hdr + cp * mc};
 }
 
-// Rebuild and upload the cohorts: active jets in slot order, a new cohort
-// whenever the next jet's buffers would take the cohort past cohort_bytes.
-// Written into the copy of the lists that the groups in flight do not read.
+// Rebuild and upload the cohorts: active jets by storage form (the batch's
+// first), in slot order within a form; a new cohort at every change of form
+// and whenever the next jet's buffers would take the cohort past
+// cohort_bytes.  Written into the copy of the lists that the groups in
+// flight do not read.
 int rebuild(lbm_batch *b) {
-  const int shape = pick_shape(b);
   const int32_t ms = (int32_t)b->slots.size();
+  std::vector<int32_t> order;
+  for (int32_t s = 0; s < ms; ++s)
+    if (b->slots[s].used && b->slots[s].step < b->slots[s].target) order.push_back(s);
+  // by storage form, the batch's first; slot order within a form
+  const auto form_key = [&](int32_t s) {
+    const int p = b->slots[s].prec;
+    return std::make_pair(p != b->prec, p);
+  };
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t x, int32_t y) { return form_key(x) < form_key(y); });
+  // storage forms after each position's own (cohorts kept for them: a form
+  // change always opens a cohort; max_cohorts >= the forms present, since it
+  // is at least min(max_slots, 64))
+  std::vector<int32_t> later(order.size(), 0);
+  for (size_t q = order.size(); q-- > 1;)
+    later[q - 1] = later[q] + (b->slots[order[q]].prec != b->slots[order[q - 1]].prec ? 1 : 0);
   std::vector<std::vector<JetDesc>> jets(1);
   std::vector<std::vector<int32_t>> start(1, std::vector<int32_t>(1, 0));
   std::vector<size_t> bytes(1, 0);
+  std::vector<lbm_batch::Cohort> meta(1);
   b->active.clear();
-  for (int32_t s = 0; s < ms; ++s) {
+  for (size_t q = 0; q < order.size(); ++q) {
+    const int32_t s = order[q];
     Slot &sl = b->slots[s];
-    if (!sl.used || sl.step >= sl.target) continue;
-    if (b->cohort_bytes && !jets.back().empty() &&
-        bytes.back() + sl.bytes > b->cohort_bytes && (int32_t)jets.size() < b->max_cohorts) {
+    const bool other_form = !jets.back().empty() && meta.back().prec != sl.prec;
+    const bool full = b->cohort_bytes && !jets.back().empty() &&
+                      bytes.back() + sl.bytes > b->cohort_bytes &&
+                      (int32_t)jets.size() + later[q] < b->max_cohorts;
+    if (other_form || full) {
       jets.emplace_back();
       start.emplace_back(1, 0);
       bytes.push_back(0);
+      meta.emplace_back();
     }
+    if (jets.back().empty()) {
+      meta.back().prec = sl.prec;
+      meta.back().shape = pick_shape(b, sl.prec);
+    }
+    const int shape = meta.back().shape;
+    sl.shape = shape;
     int32_t tx;
     const int nt = tiles_of(&sl.cfg, shape, &tx);
     sl.desc.tiles_x = tx;
@@ -230,13 +281,14 @@ int rebuild(lbm_batch *b) {
                            b->stream));
   b->copy_cohorts[cp] = b->n_cohorts;
   b->copy = cp;
-  // persistent grid of fixed size (graphs stay valid as jets come and go):
-  // by default the workgroups the device holds at once
-  int32_t g = b->wg > 0 ? b->wg
-                        : resident_workgroups(shape, b->prec, b->layout == LBM_LAYOUT_SINGLE);
-  g = (g + 7) / 8 * 8;
-  b->grid = g;
-  b->cur_shape = shape;
+  // persistent grid of fixed size per cohort (graphs stay valid as jets come
+  // and go): by default the workgroups the device holds at once
+  for (lbm_batch::Cohort &m : meta) {
+    int32_t g = b->wg > 0 ? b->wg
+                          : resident_workgroups(m.shape, m.prec, b->layout == LBM_LAYOUT_SINGLE);
+    m.grid = (g + 7) / 8 * 8;
+  }
+  b->cohorts[cp] = meta;
   b->dirty = false;
   return LBM_OK;
 }
@@ -244,11 +296,13 @@ int rebuild(lbm_batch *b) {
 // Launch group k of cohort c on stream st (capturing its graph on the
 // capture stream the first time).
 int run_group(lbm_batch *b, int32_t k, int32_t c, hipStream_t st) {
-  const int shape = b->cur_shape;
+  const lbm_batch::Cohort &m = b->cohorts[b->copy][c];
+  const int shape = m.shape, prec = m.prec;
+  const int32_t grid = m.grid;
   int nsh;
   const int32_t np = tile_shapes(&nsh)[shape].steps == 2 ? k / 2 : 0;
   const int32_t ms = (int32_t)b->slots.size();
-  auto key = std::make_tuple((int)k, shape, (int)b->grid, (int)c, (int)b->copy);
+  auto key = std::make_tuple((int)k, shape, (int)grid, (int)c, (int)b->copy, prec);
   auto it = b->graphs.find(key);
   if (it == b->graphs.end()) {
     const Lists L = lists_of(b, b->copy);
@@ -262,13 +316,11 @@ int run_group(lbm_batch *b, int32_t k, int32_t c, hipStream_t st) {
     // k / 2 pair launches with a two-step shape (one single step if k is
     // odd), else k single steps
     for (int32_t q = 0; q < np && !rc; ++q)
-      rc = launch_step(shape, b->prec, b->grid, cs, jets, tiles, hdr, 2 * q, q & 1, 2,
-                       b->d_flags);
+      rc = launch_step(shape, prec, grid, cs, jets, tiles, hdr, 2 * q, q & 1, 2, b->d_flags);
     for (int32_t q = 2 * np; q < k && !rc; ++q)
       rc = b->layout == LBM_LAYOUT_SINGLE
-               ? launch_aa_step(b->prec, b->grid, cs, jets, tiles, hdr, q, b->d_flags)
-               : launch_step(shape, b->prec, b->grid, cs, jets, tiles, hdr, q, np & 1, 1,
-                             b->d_flags);
+               ? launch_aa_step(prec, grid, cs, jets, tiles, hdr, q, b->d_flags)
+               : launch_step(shape, prec, grid, cs, jets, tiles, hdr, q, np & 1, 1, b->d_flags);
     if (!rc) rc = launch_advance(cs, jets, hdr, ms, k, np);
     const hipError_t e = hipStreamEndCapture(cs, &g);
     if (rc || e != hipSuccess) return rc ? rc : LBM_EDEVICE;
@@ -383,7 +435,9 @@ int lbm_batch_jet_bytes(const lbm_batch *b, const lbm_config *cfg, size_t *bytes
   if (!b || !cfg || !bytes) return LBM_EINVAL;
   const int rc = validate_config(cfg, false);
   if (rc) return rc;
-  *bytes = n_buffers(b->layout) * buffer_bytes(cfg, b->prec);
+  const int prec = jet_prec(b, cfg);
+  if (!storage_form(prec)) return LBM_EINVAL;
+  *bytes = n_buffers(b->layout) * buffer_bytes(cfg, prec);
   return LBM_OK;
 }
 
@@ -411,14 +465,17 @@ int lbm_batch_admit(lbm_batch *b, const lbm_config *cfg, int32_t n_t, const doub
       break;
     }
   if (s < 0) return LBM_ENOMEM;
-  const size_t one = buffer_bytes(cfg, b->prec);
+  const int prec = jet_prec(b, cfg);
+  if (!storage_form(prec)) return LBM_EINVAL;
+  const size_t one = buffer_bytes(cfg, prec);
   const size_t need = n_buffers(b->layout) * one;
   size_t off;
   if (!b->arena.alloc(need, &off)) return LBM_ENOMEM;
   Slot &sl = b->slots[s];
   sl = Slot();
   sl.cfg = *cfg;
-  sl.cfg.precision = b->prec;
+  sl.prec = prec;
+  sl.cfg.precision = prec;
   sl.cfg.layout = b->layout;
   if (cfg->table_n > 0) {
     sl.nu_tab.assign(cfg->nu_mult, cfg->nu_mult + cfg->table_n);
@@ -471,7 +528,7 @@ int lbm_batch_admit(lbm_batch *b, const lbm_config *cfg, int32_t n_t, const doub
   d.step0 = 0;
   d.slot = s;
   int32_t tx;
-  tiles_of(&sl.cfg, pick_shape(b), &tx);
+  tiles_of(&sl.cfg, pick_shape(b, prec), &tx);
   d.tiles_x = tx;
   // Uploads and initialisation are queued on the batch's stream, behind the
   // groups in flight.  Those no longer touch this slot's memory: the jet it
@@ -491,8 +548,8 @@ int lbm_batch_admit(lbm_batch *b, const lbm_config *cfg, int32_t n_t, const doub
       make_float4((float)cfg->rho0, (float)cfg->ux0, (float)cfg->ur0, (float)cfg->T0);
   for (int64_t q = n_buffers(b->layout) - 1; q >= 0 && !rc; --q) {
     const int32_t v = state_view_of(b->layout, q, 0);
-    rc = launch_init(b->prec, b->stream, b->d_slot_desc + s, &sl.cfg, q, v, nullptr, u0);
-    if (!rc) rc = launch_ghost_fill(b->prec, b->stream, b->d_slot_desc + s, &sl.cfg, q, v);
+    rc = launch_init(prec, b->stream, b->d_slot_desc + s, &sl.cfg, q, v, nullptr, u0);
+    if (!rc) rc = launch_ghost_fill(prec, b->stream, b->d_slot_desc + s, &sl.cfg, q, v);
   }
   if (rc) return rc;
   b->used += sl.bytes;
@@ -527,10 +584,11 @@ int lbm_batch_run(lbm_batch *b, int32_t k_steps) {
   b->copy_used[b->copy] = true;
   // mirror of the advance kernel: every pair a jet took in full toggled its flip
   int nsh;
-  const int64_t np = tile_shapes(&nsh)[b->cur_shape].steps == 2 ? k_steps / 2 : 0;
+  const TileShape *shapes = tile_shapes(&nsh);
   bool finished = false;
   for (int32_t s : b->active) {
     Slot &sl = b->slots[s];
+    const int64_t np = shapes[sl.shape].steps == 2 ? k_steps / 2 : 0;
     if (sl.step >= sl.target) continue;
     if (np > 0 && sl.target - sl.step >= 2)
       sl.flip ^= (int32_t)(std::min<int64_t>(np, (sl.target - sl.step) / 2) & 1);
@@ -584,7 +642,7 @@ int lbm_batch_profiles(lbm_batch *b, int32_t slot, double *ux_axis, double *T_ax
   int rc = b->scratch.get(n * sizeof(float2), &p);
   if (rc) return rc;
   if ((rc = io_after(b, *sl))) return rc;
-  if ((rc = launch_profiles(b->prec, b->io, b->d_slot_desc + slot, &sl->cfg, sl->step,
+  if ((rc = launch_profiles(sl->prec, b->io, b->d_slot_desc + slot, &sl->cfg, sl->step,
                             state_view_of(b->layout, sl->step, sl->flip), (float2 *)p)))
     return rc;
   std::vector<float2> v(n);
@@ -610,7 +668,7 @@ int lbm_batch_moments(lbm_batch *b, int32_t slot, double *rho, double *ux, doubl
   int rc = b->scratch.get(nodes * sizeof(float4), &p);
   if (rc) return rc;
   if ((rc = io_after(b, *sl))) return rc;
-  if ((rc = launch_moments(b->prec, b->io, b->d_slot_desc + slot, &sl->cfg, sl->step,
+  if ((rc = launch_moments(sl->prec, b->io, b->d_slot_desc + slot, &sl->cfg, sl->step,
                            state_view_of(b->layout, sl->step, sl->flip), (float4 *)p)))
     return rc;
   std::vector<float4> m((size_t)nodes);

@@ -383,16 +383,20 @@ class Batch:
     def __exit__(self, *a):
         self.close()
 
-    def jet_bytes(self, params: dict) -> int:
-        cfg, keep = make_config(params, self.precision)
+    def jet_bytes(self, params: dict, precision: str | None = None) -> int:
+        """Budget bytes of a jet in `precision` (default: the batch's)."""
+        cfg, keep = make_config(params, precision or self.precision)
         n = ctypes.c_size_t()
         _check(self.lib.lbm_batch_jet_bytes(self.b, ctypes.byref(cfg), ctypes.byref(n)),
                "lbm_batch_jet_bytes")
         return int(n.value)
 
-    def try_admit(self, params: dict, inlet, target_steps: int, rho_ref=1.0, g_ref=0.0):
-        """Returns (code, slot)."""
-        cfg, keep = make_config(params, self.precision, rho_ref, g_ref)
+    def try_admit(self, params: dict, inlet, target_steps: int, rho_ref=1.0, g_ref=0.0,
+                  precision: str | None = None):
+        """Returns (code, slot).  precision: the jet's storage form (default:
+        the batch's); a batch holds jets of several forms, each form in
+        cohorts of its own."""
+        cfg, keep = make_config(params, precision or self.precision, rho_ref, g_ref)
         slot = ctypes.c_int32(-1)
         if inlet is None:
             rc = self.lib.lbm_batch_admit(self.b, ctypes.byref(cfg), 0, None, None, None,

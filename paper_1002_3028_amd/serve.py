@@ -21,7 +21,6 @@ from __future__ import annotations
 
 import argparse
 import collections
-import contextlib
 import json
 import math
 import time
@@ -62,53 +61,48 @@ def serve(requests, precision: str = "fp16", budget_bytes: int = 16 << 30,
     so a budget holds twice as many jets.
 
     Requests run in `precision`, except that with FP16 storage those of more
-    than `long_after` steps run in `long_storage` (route); each
-    storage form has its own batch, the budget and the slot count bound them
-    together, and all batches advance together.
+    than `long_after` steps run in `long_storage` (route): one batch holds
+    both, each storage form in cohorts of its own.
 
     realtime=False admits every request at t = 0 (saturation: measures the
     capacity).  pipeline=False waits for each group before the host retires
-    and admits (the device idles meanwhile).  streams (1 to 4) and cohort_bytes override the batch's
-    defaults when given.  Returns a summary dict, plus per-request records.
+    and admits (the device idles meanwhile).  streams (1 to 4) and
+    cohort_bytes override the batch's defaults when given.  Returns a summary
+    dict, plus per-request records.
     """
     order = sorted(range(len(requests)), key=lambda q: requests[q][0])
     pending = collections.deque(order)
-    live = {}  # (storage, slot) -> request index
+    live = {}  # slot -> request index
     rec = [None] * len(requests)
     updates = 0
     groups = 0
     peak_slots = 0
     peak_bytes = 0
-    precs = sorted({route(precision, r[3], long_after, long_storage) for r in requests})
-    with contextlib.ExitStack() as stack:
-        batches = {}
-        for pr in precs:
-            b = stack.enter_context(lbm.Batch(budget_bytes, max_slots, pr, layout=layout))
-            b.set_launch(tile_shape, workgroups)
-            if streams:
-                b.set_streams(streams)
-            if cohort_bytes >= 0:
-                b.set_cohort_bytes(cohort_bytes)
-            batches[pr] = b
+    with lbm.Batch(budget_bytes, max_slots, precision, layout=layout) as b:
+        b.set_launch(tile_shape, workgroups)
+        if streams:
+            b.set_streams(streams)
+        if cohort_bytes >= 0:
+            b.set_cohort_bytes(cohort_bytes)
         t0 = time.perf_counter()
 
         def now():
             return time.perf_counter() - t0
 
-        def finish(keys):
+        def finish(slots):
             nonlocal updates
-            for key in keys:
-                q = live.pop(key)
-                prof = batches[key[0]].profiles(key[1])  # waits for the group it finished in
+            for slot in slots:
+                q = live.pop(slot)
+                prof = b.profiles(slot)  # waits for the group it finished in
                 t_done = now()
-                batches[key[0]].retire(key[1])
+                b.retire(slot)
                 rec[q]["completed"] = t_done
                 rec[q]["latency"] = t_done - rec[q]["arrival"]
                 updates += rec[q]["nodes"] * rec[q]["steps"]
                 if keep_profiles:
                     rec[q]["profiles"] = prof
 
-        finished_prev = []  # (storage, slot) of jets that finished in the last group queued
+        finished_prev = []  # slots of jets that finished in the last group queued
         host = collections.Counter()  # host seconds by phase
         while pending or live:
             t = now()
@@ -116,42 +110,33 @@ def serve(requests, precision: str = "fp16", budget_bytes: int = 16 << 30,
                 q = pending[0]
                 arr, p, inlet, steps = requests[q]
                 pr = route(precision, steps, long_after, long_storage)
-                if len(batches) > 1:  # the budget and slots bound all batches together
-                    act = [b.active() for b in batches.values()]
-                    if (sum(a[0] for a in act) >= max_slots or
-                            sum(a[1] for a in act) + batches[pr].jet_bytes(p) > budget_bytes):
-                        break
-                rc, slot = batches[pr].try_admit(p, inlet, steps)
+                rc, slot = b.try_admit(p, inlet, steps, precision=pr)
                 if rc == lbm.ENOMEM:
                     break
                 if rc != lbm.OK:
                     raise lbm.LbmError(rc, "lbm_batch_admit", lbm.strerror(rc))
-                live[(pr, slot)] = q
+                live[slot] = q
                 pending.popleft()
                 rec[q] = {"arrival": arr if realtime else 0.0, "admitted": now(),
                           "nodes": p["nx"] * p["nr"], "steps": steps, "storage": pr}
-            act = [b.active() for b in batches.values()]
-            peak_slots = max(peak_slots, sum(a[0] for a in act))
-            peak_bytes = max(peak_bytes, sum(a[1] for a in act))
-            running = [k for k, q in live.items() if batches[k[0]].poll(k[1]) < rec[q]["steps"]]
+            n_act, used = b.active()
+            peak_slots = max(peak_slots, n_act)
+            peak_bytes = max(peak_bytes, used)
+            running = [s for s, q in live.items() if b.poll(s) < rec[q]["steps"]]
             t1 = now()
             host["admit"] += t1 - t
             if running:
                 # queue the next group first: the device runs it while the
                 # host retires the jets of the previous group and admits
-                ran = sorted({k[0] for k in running})
-                for pr in ran:
-                    batches[pr].run(k_steps)
+                b.run(k_steps)
                 t2 = now()
-                for pr in ran:
-                    # the previous group (this one runs on), or this one when
-                    # not pipelined
-                    batches[pr].wait(1 if pipeline else 0)
+                # the previous group (this one runs on), or this one when not
+                # pipelined
+                b.wait(1 if pipeline else 0)
                 t3 = now()
                 groups += 1
                 finish(finished_prev)
-                finished_prev = [k for k in running
-                                 if batches[k[0]].poll(k[1]) >= rec[live[k]]["steps"]]
+                finished_prev = [s for s in running if b.poll(s) >= rec[live[s]]["steps"]]
                 if not pipeline:
                     finish(finished_prev)
                     finished_prev = []
@@ -159,7 +144,7 @@ def serve(requests, precision: str = "fp16", budget_bytes: int = 16 << 30,
                 host["wait"] += t3 - t2
                 host["finish"] += now() - t3
             else:
-                finish(finished_prev + [k for k in live if k not in finished_prev])
+                finish(finished_prev + [s for s in live if s not in finished_prev])
                 finished_prev = []
                 if pending and realtime:
                     time.sleep(max(0.0, min(requests[pending[0]][0] - now(), 0.01)))

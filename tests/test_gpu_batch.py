@@ -60,6 +60,32 @@ def test_alone_equals_in_mix(precision, cohort, streams):
             assert np.array_equal(m[key], mixed[slots[q]][key]), (q, key)
 
 
+@pytest.mark.parametrize("cohort", [0, 1 << 20])
+def test_storage_forms_mixed_in_one_batch(cohort):
+    """Jets of four storage forms in one batch (its own FP16 and three
+    others, admitted in interleaved order): each form runs in cohorts of its
+    own, and every jet's result is bitwise the same as alone in a batch of
+    its form."""
+    from paper_1002_3028_amd import lbm
+    jets = _jets()
+    forms = ["fp32", "fp16sr", "fp16", "bf16", "fp16sr"]
+    with lbm.Batch(1 << 30, 16, "fp16") as mix:
+        mix.set_cohort_bytes(cohort)
+        slots = [mix.admit(p, inlet, steps, precision=forms[q])
+                 for q, (p, inlet, steps) in enumerate(jets)]
+        for _ in range(12):
+            mix.run(10)
+        assert [mix.poll(s) for s in slots] == [steps for _, _, steps in jets]
+        mixed = _moments_after(mix, slots)
+    for q, (p, inlet, steps) in enumerate(jets):
+        with lbm.Batch(1 << 28, 2, forms[q]) as alone:
+            s = alone.admit(p, inlet, steps)
+            alone.run(steps + 5)
+            m = alone.moments(s)
+        for key in m:
+            assert np.array_equal(m[key], mixed[slots[q]][key]), (q, forms[q], key)
+
+
 def test_batch_matches_single_solver_and_oracle():
     """A batched jet equals the single-jet solver bitwise and the oracle to
     the FP32 tolerance."""

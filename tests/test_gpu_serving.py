@@ -62,9 +62,9 @@ def test_budget_limits_concurrency():
 
 
 def test_long_requests_route_to_stochastic_rounding():
-    """With FP16 storage, requests longer than the step limit run in their own
-    FP16SR batch; every result equals its alone run in the storage it was
-    routed to, and the budget and slot count bound both batches together."""
+    """With FP16 storage, requests longer than the step limit run in FP16SR
+    cohorts of the same batch; every result equals its alone run in the
+    storage it was routed to, within the one budget and slot count."""
     from paper_1002_3028_amd import lbm, serve
     trace = _small_trace()
     limit = int(np.median([t[3] for t in trace]))
