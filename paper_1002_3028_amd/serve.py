@@ -111,6 +111,10 @@ def serve(requests, precision: str = "fp16", budget_bytes: int = 16 << 30,
                 arr, p, inlet, steps = requests[q]
                 pr = route(precision, steps, long_after, long_storage)
                 rc, slot = b.try_admit(p, inlet, steps, precision=pr)
+                if rc == lbm.ENOMEM and not live:
+                    raise lbm.LbmError(rc, "lbm_batch_admit",
+                                       f"request {q} ({p['nx']} x {p['nr']}, {pr}) does not fit "
+                                       "an empty batch: budget or slot count too small")
                 if rc == lbm.ENOMEM:
                     break
                 if rc != lbm.OK:
