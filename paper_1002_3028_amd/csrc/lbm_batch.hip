@@ -18,9 +18,10 @@
 // it retires and admits jets: the cohort lists exist twice (a rebuild writes
 // the copy that the groups in flight do not read), every group records an
 // event, profiles are extracted on a stream of their own after the group in
-// which the jet finished, and admission and retirement neither allocate nor
-// wait for the batch's stream (each slot keeps its block for the property
-// table and inlet rows from one jet to the next).
+// which the jet finished, and admission and retirement do not wait for the
+// batch's stream (each slot keeps its block for the property table and inlet
+// rows from one jet to the next, so admission allocates only when a jet
+// needs more than any earlier jet of its slot).
 #include <algorithm>
 #include <cstring>
 #include <map>

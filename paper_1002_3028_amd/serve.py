@@ -4,12 +4,15 @@ Requests (a jet configuration, its inlet rows and a step count) arrive over
 time.  A request is admitted as soon as it has arrived, a slot is free and
 its two population buffers fit the HBM budget; its populations stay resident
 on the device until it finishes.  All resident jets advance together, k
-steps per group, in one persistent launch per step.  The loop queues each
+steps per group, in one persistent launch per step for each cohort of
+jets (one storage form per cohort).  The loop queues each
 group before it handles the previous one, so the device is not left idle
 while the host works: the jets that reached their step count in the previous
 group return their centreline and exit-column profiles of u_x and T and free
 their slot and memory, and requests that arrived meanwhile are admitted and
-join the next group queued.
+join the next group queued.  FP16 requests of more than FP16_STEP_LIMIT steps
+run with stochastic rounding (route), whose temperature stays within 1 % at
+any run length.
 
 Latency is completion minus arrival (wall clock); completion is taken when
 the device has finished the group in which the jet reached its step count.
