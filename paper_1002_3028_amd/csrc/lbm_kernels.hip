@@ -130,7 +130,8 @@ int make_inlet(const lbm_config *c, int32_t n_t, const double *ux, const double 
     (const void *)&step_kernel<CodecF16, BX, BY, NY, NX, W, CP>,                 \
     (const void *)&step_kernel<CodecBF16, BX, BY, NY, NX, W, CP>,                \
     (const void *)&step_kernel<CodecF16SR, BX, BY, NY, NX, W, CP>}}
-// two steps per launch: 64 x TY tiles, block 64 x NW
+// two steps per launch: 64 x TY tiles, block 64 x NW (lds: the LDS image of
+// FP32 storage; the 16-bit forms keep theirs in the storage type, half that)
 #define LBM_PAIR(TY, NW, W, CP)                                                  \
   {64, NW, (TY) / (NW), 1, W, CP, 2, (NPOP - ((CP) & 8 ? 1 : 0)) * ((TY) + 2) * PAIR_W * 4, \
    {(const void *)&pair_kernel<CodecF32, TY, NW, W, CP>,                         \
@@ -149,6 +150,10 @@ static const TileShape kShapes[] = {
     LBM_PAIR(12, 4, 3, 4),         LBM_PAIR(8, 4, 4, 5),          LBM_PAIR(16, 4, 2, 4),
     LBM_PAIR(8, 4, 5, 8),          LBM_PAIR(8, 4, 5, 9),          LBM_PAIR(8, 4, 5, 12),
     LBM_PAIR(12, 4, 3, 8),
+    // 16-bit storage: a 64 x 16 tile's image (28.5 KB) leaves room for five
+    // workgroups per CU, and the 1 024 tiles of a 2048 x 512 jet then fit
+    // the resident workgroups at once (no second, partly idle round)
+    LBM_PAIR(16, 4, 5, 8),         LBM_PAIR(16, 4, 5, 12),
 };
 #undef LBM_SHAPE
 #undef LBM_PAIR

@@ -255,9 +255,10 @@ __device__ __forceinline__ bool is_edge(const JetDesc &d, int i, int j) {
 
 // LDS image of the intermediate state of a two-step launch: per plane,
 // EH = TY + 2 rows of PAIR_W = 66 columns, position (x, y) holding node
-// (ia - 1 + x, ja - 1 + y).  Values are kept as the next step would decode
-// them from storage.  put() is the epilogue's destination: writes outside
-// the image are dropped.
+// (ia - 1 + x, ja - 1 + y).  Values are kept in the storage type, encoded as
+// a store to memory would encode them, and decoded when step 2 pulls them,
+// so the image of 16-bit storage takes half the LDS of FP32's.  put() is the
+// epilogue's destination: writes outside the image are dropped.
 constexpr int PAIR_W = 66;
 
 // Planes below P0 are not kept (P0 = 1: the rest population stays in the
@@ -270,12 +271,12 @@ __device__ __forceinline__ float storage_round(const JetDesc &d, int p, float v,
 
 template <class C, int EH, int P0>
 struct LdsImage {
-  float *s;
+  typename C::T *s;
   int ia, ja;
   int wrap;  // nx for periodic x edges (a column nx away is the same column), else 0
   __device__ __forceinline__ void set(const JetDesc &d, int p, int x, int y, float v,
                                      uint32_t k) const {
-    if (p >= P0) s[((p - P0) * EH + y) * PAIR_W + x] = storage_round<C>(d, p, v, k);
+    if (p >= P0) s[((p - P0) * EH + y) * PAIR_W + x] = C::enc(v, pop_offset<C>(d, p), k);
   }
   __device__ __forceinline__ void put(const JetDesc &d, int p, int i, int j, float v,
                                      uint32_t k) const {
@@ -323,7 +324,7 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(W, 8)))
   // 2), so the image holds 12 planes
   constexpr int P0 = (CP & 8) ? 1 : 0;
   static_assert(TY % NW == 0 && 2 * EH <= 64, "tile rows");
-  __shared__ float img[(NPOP - P0) * EH * PAIR_W];
+  __shared__ T img[(NPOP - P0) * EH * PAIR_W];
   const int lane = (int)threadIdx.x, wave = (int)threadIdx.y;
   const int32_t njets = hdr->njets;
   const int32_t ntiles = tile_start[njets];
@@ -401,9 +402,10 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(W, 8)))
           const bool ring = (i >= -1) & (i <= nx) & (j >= -1) & (j <= nr) &
                             ((!px & ((i == -1) | (i == nx))) | (j == -1) | (j == nr));
           if (ring) {
-            float v[NPOP];
+            T v[NPOP];
 #pragma unroll
-            for (int p = P0; p < NPOP; ++p) v[p] = src.load(d, p, i, j);
+            for (int p = P0; p < NPOP; ++p)
+              v[p] = src.base[(int64_t)p * src.plane + node_index(src.pitch, i, j)];
 #pragma unroll
             for (int p = P0; p < NPOP; ++p) img[((p - P0) * EH + y) * PAIR_W + x] = v[p];
           }
@@ -476,7 +478,9 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(W, 8)))
           f[0] = f0;
 #pragma unroll
           for (int p = P0; p < NPOP; ++p) {
-            const float v = img[((p - P0) * EH + r + 1 - per(p)) * PAIR_W + lane + 1 - pex(p)];
+            const float v = C::dec(
+                img[((p - P0) * EH + r + 1 - per(p)) * PAIR_W + lane + 1 - pex(p)],
+                pop_offset<C>(d, p));
             if (p < 9) f[p] = v; else g[p - 9] = v;
           }
           const float rr = d.r0 + (float)j + 0.5f;
