@@ -67,8 +67,8 @@ enum lbm_precision {
   LBM_PREC_FP16SR = 4    /* binary16 of the same deviations, rounded
                             stochastically: up with the probability of the
                             discarded fraction (values binary16 holds are
-                            kept), the random number a hash of the value's
-                            bits (reproducible)                             */
+                            kept), the random number from a hash of the
+                            node, the step and the value (reproducible)     */
 };
 
 /* Edge rules, per side: 0 = x0 (i = -1), 1 = x1 (i = nx), 2 = r0 (j = -1),
