@@ -49,13 +49,19 @@ struct Slot {
 };
 
 // Device block of a slot for its jet's property table and inlet rows; kept
-// from one jet to the next (grown when a jet needs more), so that admission
-// and retirement need no allocation, which would wait for the device.
+// from one jet to the next, so that admission needs no allocation.  The
+// first kPoolSlots slots take kBlockBytes each from one pool allocated with
+// the batch; a jet that needs more gets a larger block of its own, and the
+// block it replaces is freed only with the batch (freeing device memory
+// would wait for the device, stalling a pipelined loop).
+constexpr size_t kBlockBytes = size_t(64) << 10;  // the table and 7 inlet rows of 512 nodes
+constexpr int32_t kPoolSlots = 512;
 struct SlotBlock {
   void *p = nullptr;  // device
   void *h = nullptr;  // pinned host staging of the same size (the upload is
                       // then an asynchronous copy in stream order)
   size_t cap = 0;
+  bool own = false;   // allocated for this slot (else a part of the pool)
 };
 
 // First-fit free list over [0, size) with 256-byte granules.
@@ -107,6 +113,8 @@ struct lbm_batch {
   Arena arena;
   std::vector<Slot> slots;
   std::vector<SlotBlock> blocks;   // per slot
+  void *pool_d = nullptr, *pool_h = nullptr;  // the first slots' blocks
+  std::vector<std::pair<void *, void *>> replaced;  // blocks freed with the batch
   // cohort lists, two copies (index `copy`): per cohort the compact list of
   // its jets, the tile prefix sums and the header
   JetDesc *d_jets = nullptr;
@@ -389,6 +397,12 @@ int lbm_batch_create(size_t budget_bytes, int32_t max_slots, int32_t precision,
             hipHostMalloc(&b->h_slot, max_slots * sizeof(JetDesc), hipHostMallocDefault) ==
                 hipSuccess &&
             hipHostMalloc(&b->h_zero, sizeof(int32_t), hipHostMallocDefault) == hipSuccess;
+  const size_t pooled = (size_t)std::min(max_slots, kPoolSlots);
+  ok = ok && hipMalloc(&b->pool_d, pooled * kBlockBytes) == hipSuccess &&
+       hipHostMalloc(&b->pool_h, pooled * kBlockBytes, hipHostMallocDefault) == hipSuccess;
+  for (size_t q = 0; ok && q < pooled; ++q)
+    b->blocks[q] = SlotBlock{(char *)b->pool_d + q * kBlockBytes,
+                             (char *)b->pool_h + q * kBlockBytes, kBlockBytes, false};
   // The runtime spreads a process's streams over a few hardware queues (four
   // by default), and work on streams that share a queue runs in submission
   // order.  The batch's own streams are created back to back -- the cohort
@@ -490,26 +504,24 @@ int lbm_batch_admit(lbm_batch *b, const lbm_config *cfg, int32_t n_t, const doub
     return rc;
   }
   std::vector<float4> table = make_table(&sl.cfg);
-  // the slot's block holds the table and the inlet rows; it is grown only
-  // when a jet needs more than any earlier jet of the slot (freeing device
-  // memory waits for the device)
+  // the slot's block holds the table and the inlet rows; a jet that needs
+  // more than the block holds gets a larger one (at least twice the size),
+  // and the old one waits for the batch's end
   const size_t tb = align256(table.size() * sizeof(float4));
   const size_t ib = align256(rows.size() * sizeof(float4));
   SlotBlock &blk = b->blocks[s];
   if (blk.cap < tb + ib) {
-    if (blk.p) (void)hipFree(blk.p);
-    if (blk.h) (void)hipHostFree(blk.h);
-    blk.p = blk.h = nullptr;
-    blk.cap = 0;
-    if (hipMalloc(&blk.p, tb + ib) != hipSuccess ||
-        hipHostMalloc(&blk.h, tb + ib, hipHostMallocDefault) != hipSuccess) {
-      if (blk.p) (void)hipFree(blk.p);
-      blk.p = blk.h = nullptr;
+    const size_t cap = std::max({tb + ib, 2 * blk.cap, kBlockBytes});
+    SlotBlock nb{nullptr, nullptr, cap, true};
+    if (hipMalloc(&nb.p, cap) != hipSuccess ||
+        hipHostMalloc(&nb.h, cap, hipHostMallocDefault) != hipSuccess) {
+      if (nb.p) (void)hipFree(nb.p);
       b->arena.release(off, need);
       sl = Slot();
       return LBM_ENOMEM;
     }
-    blk.cap = tb + ib;
+    if (blk.own) b->replaced.emplace_back(blk.p, blk.h);
+    blk = nb;
   }
   sl.d_table = (float4 *)blk.p;
   sl.d_inlet = (float4 *)((char *)blk.p + tb);
@@ -765,9 +777,15 @@ void lbm_batch_destroy(lbm_batch *b) {
   if (b->io) (void)hipStreamSynchronize(b->io);
   drop_graphs(b);
   for (SlotBlock &k : b->blocks) {
-    if (k.p) (void)hipFree(k.p);
-    if (k.h) (void)hipHostFree(k.h);
+    if (k.own && k.p) (void)hipFree(k.p);
+    if (k.own && k.h) (void)hipHostFree(k.h);
   }
+  for (auto &k : b->replaced) {
+    (void)hipFree(k.first);
+    (void)hipHostFree(k.second);
+  }
+  if (b->pool_d) (void)hipFree(b->pool_d);
+  if (b->pool_h) (void)hipHostFree(b->pool_h);
   b->scratch.release();
   if (b->arena_mem) (void)hipFree(b->arena_mem);
   if (b->d_jets) (void)hipFree(b->d_jets);
