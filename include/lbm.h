@@ -283,6 +283,12 @@ int lbm_batch_moments(lbm_batch *b, int32_t slot, double *rho, double *ux,
 int lbm_batch_retire(lbm_batch *b, int32_t slot);
 /* Wait for the batch's queued work; LBM_EDEVICE on an asynchronous error. */
 int lbm_batch_sync(lbm_batch *b);
+/* Device time of the groups (from just before a group's first launch to its
+ * completion, HIP events on the batch's stream) summed over the groups that
+ * lbm_batch_wait or lbm_batch_sync found complete, and how many they were
+ * (a group more than 15 groups older than the newest queued when the batch
+ * is next waited on is not counted).  Host-side; does not wait. */
+int lbm_batch_device_time(lbm_batch *b, double *ms, int64_t *groups);
 /* Bytes a jet of this configuration (and storage form, as for
  * lbm_batch_admit) takes from the budget. */
 int lbm_batch_jet_bytes(const lbm_batch *b, const lbm_config *cfg, size_t *bytes);

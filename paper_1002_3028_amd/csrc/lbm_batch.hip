@@ -131,6 +131,11 @@ struct lbm_batch {
   static constexpr int RING = 16;
   int64_t seq = 0;                 // groups enqueued
   hipEvent_t done[RING] = {};
+  // device time of the groups: start[n % RING] before group n's launches;
+  // summed up to group `timed` - 1 when waits find them complete
+  hipEvent_t start[RING] = {};
+  int64_t timed = 0, timed_groups = 0;
+  double device_ms = 0.0;
   hipStream_t io = nullptr;        // profile and moment extraction
   hipStream_t cap = nullptr;       // graph capture (never holds work)
   hipEvent_t mark = nullptr;       // "everything enqueued so far" on `stream`
@@ -424,7 +429,8 @@ int lbm_batch_create(size_t budget_bytes, int32_t max_slots, int32_t precision,
   for (int q = 0; ok && q < 2; ++q)
     ok = hipEventCreateWithFlags(&b->copy_done[q], hipEventDisableTiming) == hipSuccess;
   for (int q = 0; ok && q < lbm_batch::RING; ++q)
-    ok = hipEventCreateWithFlags(&b->done[q], hipEventDisableTiming) == hipSuccess;
+    ok = hipEventCreateWithFlags(&b->done[q], hipEventDefault) == hipSuccess &&
+         hipEventCreateWithFlags(&b->start[q], hipEventDefault) == hipSuccess;
   if (ok) {
     *b->h_zero = 0;
     std::vector<int32_t> zeros(max_slots, 0);
@@ -577,6 +583,7 @@ int lbm_batch_run(lbm_batch *b, int32_t k_steps) {
   int rc;
   if (b->dirty && (rc = rebuild(b))) return rc;
   if (b->active.empty()) return LBM_OK;
+  LBM_HIP(hipEventRecord(b->start[b->seq % lbm_batch::RING], b->stream));
   const int32_t ns = std::max(1, std::min(b->nstreams, b->n_cohorts));
   if (ns > 1) {
     // the other streams start after everything queued so far
@@ -616,12 +623,33 @@ int lbm_batch_run(lbm_batch *b, int32_t k_steps) {
   return LBM_OK;
 }
 
+// Add the device time of the complete groups up to `newest` (their events
+// are still in the ring unless more than RING groups were queued since).
+static int collect_times(lbm_batch *b, int64_t newest) {
+  for (int64_t g = std::max(b->timed, b->seq - lbm_batch::RING); g <= newest; ++g) {
+    float ms = 0.0f;
+    LBM_HIP(hipEventElapsedTime(&ms, b->start[g % lbm_batch::RING],
+                                b->done[g % lbm_batch::RING]));
+    b->device_ms += ms;
+    ++b->timed_groups;
+  }
+  b->timed = std::max(b->timed, newest + 1);
+  return LBM_OK;
+}
+
 int lbm_batch_wait(lbm_batch *b, int32_t in_flight) {
   if (!b || in_flight < 0 || in_flight >= lbm_batch::RING) return LBM_EINVAL;
   const int64_t g = b->seq - 1 - in_flight;  // the newest group that must be done
   if (g < 0) return LBM_OK;
   LBM_HIP(hipEventSynchronize(b->done[g % lbm_batch::RING]));
   LBM_HIP(hipGetLastError());
+  return collect_times(b, g);
+}
+
+int lbm_batch_device_time(lbm_batch *b, double *ms, int64_t *groups) {
+  if (!b || !ms) return LBM_EINVAL;
+  *ms = b->device_ms;
+  if (groups) *groups = b->timed_groups;
   return LBM_OK;
 }
 
@@ -716,6 +744,10 @@ int lbm_batch_sync(lbm_batch *b) {
   if (!b) return LBM_EINVAL;
   LBM_HIP(hipStreamSynchronize(b->stream));
   LBM_HIP(hipGetLastError());
+  if (b->seq > 0) {
+    const int rc = collect_times(b, b->seq - 1);
+    if (rc) return rc;
+  }
   return LBM_OK;
 }
 
@@ -804,6 +836,8 @@ void lbm_batch_destroy(lbm_batch *b) {
   for (hipEvent_t e : b->copy_done)
     if (e) (void)hipEventDestroy(e);
   for (hipEvent_t e : b->done)
+    if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : b->start)
     if (e) (void)hipEventDestroy(e);
   if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
   if (b->fork) (void)hipEventDestroy(b->fork);

@@ -90,6 +90,7 @@ _SIGS = {
     "lbm_batch_moments": ([_vp, ctypes.c_int32, _dp, _dp, _dp, _dp], ctypes.c_int),
     "lbm_batch_retire": ([_vp, ctypes.c_int32], ctypes.c_int),
     "lbm_batch_sync": ([_vp], ctypes.c_int),
+    "lbm_batch_device_time": ([_vp, _dp, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
     "lbm_batch_jet_bytes": ([_vp, ctypes.POINTER(_Config), ctypes.POINTER(ctypes.c_size_t)],
                             ctypes.c_int),
     "lbm_batch_active": ([_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_size_t)],
@@ -450,6 +451,14 @@ class Batch:
 
     def sync(self):
         _check(self.lib.lbm_batch_sync(self.b), "lbm_batch_sync")
+
+    def device_time(self):
+        """(milliseconds, groups): device time of the groups found complete
+        by wait() or sync()."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        _check(self.lib.lbm_batch_device_time(self.b, ctypes.byref(ms), ctypes.byref(n)),
+               "lbm_batch_device_time")
+        return ms.value, n.value
 
     def active(self):
         n, used = ctypes.c_int32(), ctypes.c_size_t()

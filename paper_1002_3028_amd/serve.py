@@ -156,6 +156,8 @@ def serve(requests, precision: str = "fp16", budget_bytes: int = 16 << 30,
                 if pending and realtime:
                     time.sleep(max(0.0, min(requests[pending[0]][0] - now(), 0.01)))
         t_end = now()
+        b.sync()
+        dev_ms, dev_groups = b.device_time()
     lat = [r["latency"] for r in rec]
     first = min(r["arrival"] for r in rec)
     summary = {
@@ -174,6 +176,11 @@ def serve(requests, precision: str = "fp16", budget_bytes: int = 16 << 30,
         # host time per group, by phase: admitting, queueing the group, waiting
         # for the previous one, retiring the jets it finished
         "host_ms_per_group": {k: round(v / max(groups, 1) * 1e3, 3) for k, v in host.items()},
+        # device time of the groups (HIP events around each group) over the
+        # loop's wall time: the share of it in which the device ran a group
+        "device_ms_per_group": round(dev_ms / max(dev_groups, 1), 3),
+        "device_busy": round(dev_ms * 1e-3 / max(t_end, 1e-9), 4),
+        "timed_groups": dev_groups,
     }
     return summary, rec
 

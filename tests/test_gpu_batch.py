@@ -270,3 +270,26 @@ def test_tuned_batch_equals_default(tmp_path, monkeypatch, precision):
     for q in range(len(jets)):
         for key in out[1][q]:
             assert np.array_equal(out[0][q][key], out[1][q][key]), (q, key)
+
+
+def test_device_time_of_groups():
+    """Every group queued and then waited on is timed once: the device time
+    is positive and no more than the wall time around the groups."""
+    import time
+    from paper_1002_3028_amd import lbm
+    jets = _jets()
+    with lbm.Batch(1 << 30, 16, "fp32") as b:
+        for p, inlet, steps in jets:
+            b.admit(p, inlet, steps + 1000)
+        b.run(10)
+        b.sync()
+        ms0, n0 = b.device_time()
+        t0 = time.perf_counter()
+        for _ in range(6):
+            b.run(10)
+            b.wait(1)
+        b.sync()
+        wall_ms = (time.perf_counter() - t0) * 1e3
+        ms, n = b.device_time()
+    assert n0 == 1 and n == 7
+    assert 0.0 < ms - ms0 <= wall_ms, (ms - ms0, wall_ms)

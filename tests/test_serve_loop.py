@@ -71,6 +71,12 @@ class FakeBatch:
     def poll(self, slot):
         return self.slots[slot]["steps"]
 
+    def sync(self):
+        self.done_groups = len(self.groups)
+
+    def device_time(self):
+        return 0.5 * len(self.groups), len(self.groups)  # 0.5 ms per group
+
     def profiles(self, slot):
         s = self.slots[slot]
         # the extraction waits for the group in which the jet finished
@@ -116,6 +122,7 @@ def test_every_request_served_once(fake, pipeline):
         assert r["profiles"]["prec"] == r["storage"]
         assert r["profiles"]["ux_axis"][0] == steps and r["completed"] >= r["admitted"]
     assert sorted(t for _, t in b.retired) == sorted(s for *_, s in trace)
+    assert summary["timed_groups"] == len(b.groups) and summary["device_ms_per_group"] == 0.5
     # the pipelined loop keeps one group queued ahead, the synchronous none
     assert b.max_in_flight == (2 if pipeline else 1)
 
