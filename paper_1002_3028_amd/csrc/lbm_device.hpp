@@ -163,36 +163,31 @@ __device__ __forceinline__ uint32_t plane_key(uint32_t key, int p) {
   return __builtin_amdgcn_alignbit(key, key, (uint32_t)(7 * p) & 31u);
 }
 
-// binary16 deviations with stochastic rounding: the magnitude rounds toward
-// zero after adding r times its FP32 ulp, r in [0, 2^13) the top 13 bits of
-// the value's bits xor its rounding key.  Where binary16 is normal its
-// spacing is 2^13 FP32 ulps, the sum is exact, and over keys drawn uniformly
-// the value rounds up with exactly the probability of the discarded fraction
-// (whatever the value: xor with a uniform key makes r uniform); values
-// binary16 holds are stored unchanged.  Below 2^-14 the offset spans the
-// fixed spacing 2^-24 in steps of 2^-37.  The key changes with the node and
-// the step, so a value that recurs at one node rounds independently at every
-// step and the systematic error that rounding to nearest leaves in nearly
-// steady regions averages out.  Populations of one node with equal top bits
-// share the key's bits in part (rotations of one 32-bit key): their
-// roundings are correlated but each is unbiased.  All thirteen planes are
-// rounded this way (the flow populations need it too: rounded to nearest
-// they shift the mean flow of a long run).  The sign is put back before the
-// truncation, which rounds toward zero on either side.  Decoding is
+// binary16 deviations with stochastic rounding, by gfx950's conversion for
+// it (v_cvt_sr_f16_f32): the magnitude of the deviation rounds toward zero
+// after adding r / 2^13 of the binary16 spacing at that magnitude, r the top
+// 13 bits of the second operand, for normal and subnormal binary16 results
+// alike (and the sign is kept).  The operand is the value's bits xor its
+// rounding key, so over keys drawn uniformly r is uniform whatever the value
+// and the value rounds up with the probability of its discarded fraction (to
+// 2^-13); values binary16 holds are stored unchanged.  The key changes with
+// the node and the step, so a value that recurs at one node rounds
+// independently at every step and the systematic error that rounding to
+// nearest leaves in nearly steady regions averages out.  Populations of one
+// node with equal top bits share the key's bits in part (rotations of one
+// 32-bit key): their roundings are correlated but each is unbiased.  All
+// thirteen planes are rounded this way (the flow populations need it too:
+// rounded to nearest they shift the mean flow of a long run).  Decoding is
 // binary16's.
 struct CodecF16SR {
   using T = _Float16;
   static constexpr bool dev = true;
   __device__ static __forceinline__ float dec(T v, float off) { return (float)v + off; }
   __device__ static __forceinline__ T enc(float v, float off, uint32_t key) {
+    typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
     const float x = v - off;
-    const uint32_t xb = __builtin_bit_cast(uint32_t, x);
-    const uint32_t ab = xb & 0x7fffffffu;
-    const float r = (float)((xb ^ key) >> 19);
-    // FP32 ulp of |x| (its binade times 2^-23), at least 2^-37
-    const float ulp = fmaxf(__builtin_bit_cast(float, ab & 0x7f800000u) * 0x1p-23f, 0x1p-37f);
-    const uint32_t y = __builtin_bit_cast(uint32_t, __builtin_fmaf(r, ulp, __builtin_bit_cast(float, ab)));
-    return __builtin_amdgcn_cvt_pkrtz(__builtin_bit_cast(float, y | (xb & 0x80000000u)), 0.0f)[0];
+    const uint32_t r = __builtin_bit_cast(uint32_t, x) ^ key;
+    return __builtin_amdgcn_cvt_sr_f16_f32(half2_t{0, 0}, x, r, false)[0];
   }
 };
 struct CodecBF16 {
