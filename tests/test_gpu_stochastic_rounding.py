@@ -13,7 +13,12 @@ directly.  Properties checked:
 * the rounding key is the node's and the step's: one value stored at every
   node rounds up at a share of them equal to its discarded fraction, writing
   the same data for the same step gives the same bits, and writing it for
-  another step draws new keys (reproducible, and independent over steps).
+  another step draws new keys (reproducible, and independent over steps);
+* bit for bit, the stored number is what an independent model of the rule
+  gives: the node and step hashed by the lowbias32 mixer, rotated by 7 bits
+  per population, xor the value's FP32 bits; the top 13 bits r of that
+  operand round the magnitude up when its discarded fraction of the binary16
+  spacing plus r / 2^13 reaches one (normal and subnormal binary16 alike).
 """
 import numpy as np
 import pytest
@@ -113,6 +118,50 @@ def test_one_value_everywhere(solver, phi):
     sd = np.sqrt(phi * (1 - phi) / N)
     print(f"phi {phi}: {up:.4f} up of {N} (sd {sd:.4f})")
     assert abs(up - phi) < 5 * sd
+
+
+def _lowbias32(x):
+    """The lowbias32 integer mixer (C. Wellons, hash-prospector), on uint64
+    arrays holding 32-bit values."""
+    m = np.uint64(0xFFFFFFFF)
+    x = x ^ (x >> np.uint64(16))
+    x = (x * np.uint64(0x7FEB352D)) & m
+    x = x ^ (x >> np.uint64(15))
+    x = (x * np.uint64(0x846CA68B)) & m
+    return x ^ (x >> np.uint64(16))
+
+
+def _model_sr(v32, plane, step):
+    """Binary16 value that stochastic rounding stores for FP32 values v32 of
+    one population plane (shape NR x NX, node (i, j) at [j, i]) written for
+    `step`, with a zero offset."""
+    m = np.uint64(0xFFFFFFFF)
+    j, i = np.meshgrid(np.arange(NR, dtype=np.uint64), np.arange(NX, dtype=np.uint64),
+                       indexing="ij")
+    key = _lowbias32(((j << np.uint64(16)) | i) ^ ((np.uint64(step) * np.uint64(0x9E3779B9)) & m))
+    s = np.uint64((7 * plane) % 32)
+    key = ((key >> s) | (key << (np.uint64(32) - s))) & m if s else key
+    bits = v32.view(np.uint32).astype(np.uint64)
+    r = ((bits ^ key) >> np.uint64(19)).astype(np.float64)
+    a = np.abs(v32.astype(np.float64))
+    # binary16 spacing at |v|: 2^(e - 10) in the normal range, 2^-24 below it
+    e = np.frexp(a)[1] - 1  # a = 1.m * 2^e
+    spacing = np.where(a >= 2.0 ** -14, np.ldexp(1.0, e - 10), 2.0 ** -24)
+    lo = np.floor(a / spacing) * spacing
+    up = (a - lo) / spacing + r / 8192.0 >= 1.0
+    return np.sign(v32.astype(np.float64)) * (lo + up * spacing)
+
+
+@pytest.mark.parametrize("step", [0, 7, 123457])
+def test_rounding_rule_bitwise(solver, step):
+    rng = np.random.default_rng(14 + step)
+    v = 2.0 ** rng.uniform(-26, -1, N) * np.where(rng.integers(0, 2, N) == 1, -1.0, 1.0)
+    v32 = v.astype(np.float32).reshape(4, NR, NX)
+    got = _round_trip(solver, v32.astype(np.float64), step).reshape(4, NR, NX)
+    for k in range(4):
+        want = _model_sr(v32[k], 9 + k, step)
+        bad = int(np.sum(got[k] != want))
+        assert bad == 0, (k, bad)
 
 
 def test_reproducible(solver):
