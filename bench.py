@@ -217,13 +217,13 @@ def roofline_block(prec, info, nodes, ms_step, traffic_name, trace_name=None, ta
     return out
 
 
-def bench_batch(n_jets=64, steps=5000, precision="fp32"):
+def bench_batch(n_jets=64, steps=5000, precision="fp32", looped=True):
     """64 jets of uneven sizes (seed 2) advanced together, one persistent
     launch per step (or pair of steps) per cohort, with the launch
     configuration the batch tuner picks for this set (tile shape, grid,
     cohort size, streams; tuned once and cached) and, for comparison, with
-    the batch's defaults; against the same jets run one after another
-    through the single-jet path.  Aggregate GLUPS of each."""
+    the batch's defaults; with `looped`, against the same jets run one after
+    another through the single-jet path.  Aggregate GLUPS of each."""
     import torch
     from paper_1002_3028_amd import autotune, inputs, lbm
 
@@ -252,6 +252,8 @@ def bench_batch(n_jets=64, steps=5000, precision="fp32"):
            "tuned_shape": lbm.tile_shape_info(tuned["shape"]),
            "batched_glups": round(batched(tuned), 3),
            "batched_default_glups": round(batched(None), 3)}
+    if not looped:
+        return out
     solvers = []
     for p, inlet, _ in jets:
         s = lbm.Solver(p, precision, graph_steps=50)
@@ -516,6 +518,9 @@ def main():
                                 for tag, pp in (("2048x512_fp32", p), ("4096x1024_fp32", pl))}
         log("64-jet batch")
         extra["batch_64_jets"] = bench_batch(steps=args.batch_steps)
+        log("64-jet batch, FP16 storage")
+        extra["batch_64_jets_fp16"] = bench_batch(steps=args.batch_steps, precision="fp16",
+                                                  looped=False)
         log("serving")
         extra["serving"] = bench_serving(args.serving_requests)
         line["extra"] = extra

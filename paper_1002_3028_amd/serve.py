@@ -197,6 +197,8 @@ def main():
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--layout", choices=["two", "single"], default="two")
     ap.add_argument("--streams", type=int, default=0, help="1 to 4 (0: the batch's default)")
+    ap.add_argument("--tile-shape", type=int, default=-1,
+                    help="tile shape index for every storage form (-1: the batch's default)")
     ap.add_argument("--cohort-mib", type=int, default=-1,
                     help="cohort limit in MiB (-1: the batch's default, 0: one cohort)")
     ap.add_argument("--sweep", default="",
@@ -216,7 +218,8 @@ def main():
         cap, _ = serve(inputs.arrival_trace(args.requests, args.seed, rate=1.0), args.precision,
                        budget, args.slots, args.k, realtime=False, layout=args.layout,
                        streams=args.streams, cohort_bytes=cohort, long_after=args.long_after,
-                       long_storage=args.long_storage, pipeline=not args.sync)
+                       long_storage=args.long_storage, pipeline=not args.sync,
+                       tile_shape=args.tile_shape)
         print(json.dumps({"saturated": cap}), flush=True)
     fractions = [float(x) for x in args.sweep.split(",") if x] if args.sweep else [None]
     for frac in fractions:
@@ -228,7 +231,8 @@ def main():
         summary, _ = serve(trace, args.precision, budget, args.slots, args.k, realtime=True,
                            layout=args.layout, streams=args.streams, cohort_bytes=cohort,
                            long_after=args.long_after,
-                           long_storage=args.long_storage, pipeline=not args.sync)
+                           long_storage=args.long_storage, pipeline=not args.sync,
+                           tile_shape=args.tile_shape)
         summary["rate"] = rate
         if frac is not None:
             summary["fraction_of_capacity"] = frac
