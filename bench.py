@@ -141,9 +141,9 @@ def time_jet(params, inlet, precision, steps, warmup, check_every=1000, tile_sha
 
     Launches: for 200 steps or more, HIP graphs of graph_group(steps) steps,
     captured (and replayed once, dry) when the solver is set up; for shorter
-    timed regions, directly launched groups (the same launches, one advance
-    at the end), which start the device on the first kernel instead of after
-    the whole graph has been submitted.  The check's cost is measured first
+    timed regions, directly launched groups (the same launches, offset from
+    the descriptor, with no advance kernel), which start the device on the
+    first kernel instead of after the whole graph has been submitted.  The check's cost is measured first
     (median of three), then the warm-up runs, so the device is busy up to the
     timed region; the timed region is bracketed by device syncs.  The check
     runs inside it after every full `check_every` steps; a remainder of r
