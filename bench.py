@@ -279,8 +279,9 @@ def bench_serving(n_requests=2000):
     FP32 and FP16 storage (every request admitted at once), then the same
     trace at one arrival rate, 0.7 x the FP32 capacity: p50/p99 latency
     (arrival to completion) and throughput.  FP16 as served by default
-    routes requests longer than the FP16 step limit to FP16 with stochastic
-    rounding (serve.route); "fp16_unrouted" keeps every request in FP16."""
+    stores requests longer than the FP16 step limit (every request: the limit
+    is 0) with stochastic rounding (serve.route); "fp16_unrouted" keeps every
+    request in FP16 rounded to nearest."""
     from paper_1002_3028_amd import inputs, serve
 
     out = {"requests": n_requests, "trace_seed": 3,
@@ -297,8 +298,8 @@ def bench_serving(n_requests=2000):
     rate = 0.7 * cap["fp32"]["requests_per_s"]
     out["rate_req_per_s"] = round(rate, 3)
     trace = inputs.arrival_trace(n_requests, 3, rate=rate)
-    for name, prec, long_after in (("fp32", "fp32", 0), ("fp16", "fp16", serve.FP16_STEP_LIMIT),
-                                   ("fp16_unrouted", "fp16", 0)):
+    for name, prec, long_after in (("fp32", "fp32", -1), ("fp16", "fp16", serve.FP16_STEP_LIMIT),
+                                   ("fp16_unrouted", "fp16", -1)):
         log(f"serving {name}: {rate:.1f} requests/s")
         run, _ = serve.serve(trace, prec, 16 << 30, 256, 100, realtime=True,
                              long_after=long_after)

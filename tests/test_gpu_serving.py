@@ -39,7 +39,10 @@ def test_result_alone_equals_in_mix(precision):
     for q, (arr, p, inlet, steps) in enumerate(trace):
         r = rec[q]
         assert r["completed"] >= r["admitted"] >= 0.0 and r["latency"] > 0.0
-        with lbm.Batch(1 << 26, 1, precision) as alone:
+        # by default FP16 requests are stored with stochastic rounding
+        assert r["storage"] == serve.route(precision, steps) == \
+            ("fp16sr" if precision == "fp16" else precision)
+        with lbm.Batch(1 << 26, 1, r["storage"]) as alone:
             s = alone.admit(p, inlet, steps)
             alone.run(steps)
             prof = alone.profiles(s)

@@ -37,12 +37,15 @@ def test_noise_is_seeded():
 
 
 def test_serving_route():
-    """Only FP16 requests longer than the step limit change storage; 0 turns
-    routing off."""
+    """Only FP16 requests longer than the step limit change storage (by
+    default every one); a negative limit turns routing off."""
     from paper_1002_3028_amd import serve
     lim = serve.FP16_STEP_LIMIT
-    assert serve.route("fp16", lim) == "fp16"
     assert serve.route("fp16", lim + 1) == "fp16sr"
-    assert serve.route("fp16", 10 * lim, long_after=0) == "fp16"
+    assert serve.route("fp16", 1000) == "fp16sr"
+    assert serve.route("fp16", 4000, long_after=4000) == "fp16"
+    assert serve.route("fp16", 4001, long_after=4000) == "fp16sr"
+    assert serve.route("fp16", 10000, long_after=-1) == "fp16"
+    assert serve.route("fp16", 10000, long_after=4000, long_storage="fp32") == "fp32"
     for prec in ("fp32", "bf16", "fp16sr"):
-        assert serve.route(prec, 10 * lim) == prec
+        assert serve.route(prec, 10000) == prec

@@ -144,7 +144,7 @@ def test_budget_smaller_than_one_jet_waits_for_room(fake):
     jets retire; requests keep their arrival order."""
     trace = _trace(12, seed=3)
     summary, rec = serve.serve(trace, "fp16", budget_bytes=1 << 20, max_slots=2, k_steps=100,
-                               realtime=False, long_after=0)
+                               realtime=False, long_after=-1)
     admitted = [r["admitted"] for r in rec]
     assert admitted == sorted(admitted)
     assert summary["peak_slots"] <= 2
