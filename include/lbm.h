@@ -65,10 +65,11 @@ enum lbm_precision {
   LBM_PREC_FP16DEV = 2,  /* binary16 of f_k - w_k rho_ref, g_k - g_ref/4     */
   LBM_PREC_BF16DEV = 3,  /* bfloat16 of the same deviations                  */
   LBM_PREC_FP16SR = 4    /* binary16 of the same deviations, rounded
-                            stochastically: up with the probability of the
-                            discarded fraction (values binary16 holds are
-                            kept), the random number from a hash of the
-                            node, the step and the value (reproducible)     */
+                            stochastically by gfx950's conversion: up with
+                            the probability of the discarded fraction, to
+                            2^-13 (values binary16 holds are kept), the
+                            random number from a hash of the node, the step
+                            and the value (reproducible)                    */
 };
 
 /* Edge rules, per side: 0 = x0 (i = -1), 1 = x1 (i = nx), 2 = r0 (j = -1),
