@@ -113,10 +113,18 @@ def exported_names():
 
 
 def load():
-    """Load liblbm_hip.so; raise if it is not built."""
+    """Load liblbm_hip.so; raise if it is not built.
+
+    torch is imported first.  The binding takes device memory and streams
+    from torch, whose wheel carries its own HIP runtime, and the library must
+    bind to that one: loaded first, the library would bring in the runtime
+    under /opt/rocm and torch its own, and memory that one runtime allocated
+    is unknown to the other (solver creation then fails, and the process can
+    crash later)."""
     global _lib
     if _lib is not None:
         return _lib
+    import torch  # noqa: F401  (its HIP runtime, before the library's)
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it first (python -m "
                            "paper_1002_3028_amd.build or __graft_entry__.build())")
