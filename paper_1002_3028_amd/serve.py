@@ -41,7 +41,7 @@ def percentile(xs, q):
 # Runs longer than this go from FP16 storage to FP16 with stochastic rounding
 # (route).  Rounding to nearest biases the temperature, whose profile error
 # grows linearly in time: 1.3e-3 at 1 000 steps and 8.7e-3 at 4 000 on the
-# jets of this workload, against 3.1e-4 and 7.0e-4 with stochastic rounding
+# jets of this workload, against 2.7e-4 and 7.0e-4 with stochastic rounding
 # (tests/test_gpu_run_length.py).  With gfx950's rounding conversion a batch
 # of FP16SR jets serves as many requests per second as one of FP16 jets, so
 # by default every FP16 request is stored that way.
