@@ -149,6 +149,24 @@ def test_bench_refuses_more_than_one_gpu():
     assert "one GPU" in msg["error"]
 
 
+def test_library_loads_after_torch():
+    """The binding imports torch before it loads the library, so that the
+    library binds to the HIP runtime that torch carries (a fresh interpreter
+    whose first call loads the library)."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = ("import sys; sys.path.insert(0, %r)\n"
+            "from paper_1002_3028_amd import lbm\n"
+            "assert 'torch' not in sys.modules\n"
+            "lbm.tile_shape_infos()\n"
+            "assert 'torch' in sys.modules\n"
+            "print('ok')\n" % root)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stderr[-2000:]
+
+
 # ---- the same five calls in the FP64 oracle library -----------------------
 
 @pytest.fixture(scope="module")
