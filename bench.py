@@ -464,9 +464,14 @@ def main():
                    "fp64_check_every": 1000,
                    "fp64_check_charged_s": round(t["check_charge_s"], 7),
                    "tile_shape": info},
+        # the committed trace of the same launch mode: the 20-step region of
+        # direct launches, or the last 1 000 launches of a 2 000-step run
         "roofline": roofline_block("fp32", info, nodes, t["event_ms_per_step"],
                                    f"traffic_{kernel_of(info).split('_')[0]}_fp32_2048x512.txt",
-                                   "pair_kernel_fp32_2048x512_kernel_trace.txt", tag="2048x512"),
+                                   "pair_kernel_fp32_2048x512_20steps_kernel_trace.txt"
+                                   if t["launch"] == "direct groups"
+                                   else "pair_kernel_fp32_2048x512_kernel_trace.txt",
+                                   tag="2048x512"),
     }
     if not args.no_extra:
         extra = {}
