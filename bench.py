@@ -307,7 +307,9 @@ def bench_serving(n_requests=2000):
                              long_after=long_after)
         out[name] = {"p50_s": run["p50_s"], "p99_s": run["p99_s"], "mean_s": run["mean_s"],
                      "served_req_per_s": run["requests_per_s"], "glups": run["glups"],
-                     "peak_slots": run["peak_slots"]}
+                     "peak_slots": run["peak_slots"],
+                     # share of the loop's wall time in which the device ran a group
+                     "device_busy": run["device_busy"]}
     return out
 
 
